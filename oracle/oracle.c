@@ -1,0 +1,819 @@
+/*
+ * CPU oracle for probe-grid ray tracing -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, double-precision C.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.  It shares
+ * no code with the GPU library.
+ *
+ * What it computes (paper: Overview; Methodology > Ray Tracing Using One Probe;
+ * Ray Trace Using Multiple Probes; appendix algorithms RayMarching, traceOneProbe,
+ * traceOneRaySegment, lowResolutionTracing, highResolutionTracing):
+ *
+ *   for a camera ray (X, w):
+ *     grid iterator: visit the cells of the probe grid crossed by the ray, in order,
+ *       each with its parameter interval [ta, tb]                   (Grid Iterator)
+ *     in each cell, try its 8 corner probes closest-to-the-eye first; MISS and
+ *       UNKNOWN both fall through to the next probe                 (Less Than 8 Probes)
+ *     one probe (traceOneProbe):
+ *       eye at the probe origin -> O(1) lookup of the map at oct(w) (Eye Aligned)
+ *       otherwise split [ta, tb] where the ray crosses the probe's coordinate planes
+ *       (at most 4 pieces, each inside one octant, so each projects to a straight
+ *       segment of the octahedral map) and march every piece texel by texel
+ *       (RayMarching): the first texel whose stored distance is below the ray's
+ *       distance from the probe inside that texel decides:
+ *         shadow entry (the ray is already behind the stored surface by more than
+ *         the thickness when it enters the texel) -> UNKNOWN (ray "from below")
+ *         stored normal . w < 0 -> HIT, else UNKNOWN  (highResolutionTracing)
+ *       no texel fires -> MISS
+ *     HIT -> radiance of the probe in the direction of the hit point, bilinearly
+ *       filtered (the L_o(X,w1) = L_p(w2) identity of the Overview).
+ *
+ * Readings where the paper is silent (also listed in the design notes):
+ *   - "ray distance inside a texel" is the radial distance rho(t) = |X - O + t w|;
+ *     a texel fires iff its stored distance r < max(rho_in, rho_out) over the ray's
+ *     parameter span inside the texel's cone (rho is convex in t).
+ *   - low-resolution maps are 2x2 MIN reductions; the hierarchical march (Alg.
+ *     traceOneRaySegment / lowResolutionTracing / highResolutionTracing) is then
+ *     conservative and its first level-0 fire equals the flat march.  The flat march
+ *     is the definition here; the hierarchical one runs beside it as a check and as
+ *     the fetch counter for algorithmic bytes.
+ *   - probe traces are restricted to the current cell's [ta, tb].
+ *   - the 8 cage probes are sorted by distance to the ray origin, ties by corner code.
+ *
+ * Every decisive comparison is also checked against a first-order forward error
+ * bound scaled by a unit roundoff `delta`; a ray with any near decision is flagged
+ * "in margin" (bit mask below) so a lower-precision implementation may disagree there.
+ *
+ * Build: gcc -O2 -shared -fPIC -pthread oracle.c -o liboracle.so -lm
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdatomic.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ST_MISS = 0, ST_HIT = 1, ST_UNKNOWN = 2 };
+
+#define MG_FIRE 1      /* a fire test near equality */
+#define MG_DDA 2       /* two boundary crossings (or a crossing and a segment end) nearly tie */
+#define MG_START 4     /* a segment starts near a texel boundary */
+#define MG_OCTANT 8    /* octant-split parameters nearly tie */
+#define MG_CELL 16     /* grid-iterator near ties */
+#define MG_CAGE 32     /* cage distance near tie */
+#define MG_EYE 64      /* ray origin near the eye-aligned threshold */
+#define MG_CLASS 128   /* shadow-entry or normal test near equality */
+#define MG_THIT 256    /* hit distance ill-conditioned */
+#define MG_HIER 512    /* hierarchical schedule disagreed with the flat march */
+
+typedef struct {
+    int32_t dims[3];
+    int32_t N, levels;
+    int32_t pad;
+    double origin[3], spacing[3];
+    double smin[3], smax[3];
+    const float *dist;      /* [P][N][N] radial distance, texel (i,j) at j*N+i */
+    const uint16_t *nrm;    /* [P][N][N][2] FP16 bits: octahedral (u,v) of the normal */
+    const float *rad;       /* [P][N][N][3] radiance (FP16 values widened, or any values) */
+    const float *mips;      /* levels 1..L-1, level l block at mip_off[l]: [P][N>>l][N>>l] */
+    const int64_t *mip_off; /* [levels] (entry 0 unused) */
+} grid_t;
+
+typedef struct {
+    double thickness_rel;  /* tau: shadow-entry thickness, relative */
+    double eye_eps_rel;    /* eye-aligned threshold, relative to min spacing */
+    double background[3];  /* colour of non-HIT rays */
+    double delta;          /* unit roundoff of the margin test */
+    int32_t max_probes_per_cell;
+    int32_t check_hier;    /* also run the hierarchical schedule and compare */
+    int32_t top_level;     /* hierarchical start level, <0 = levels-1 */
+    int32_t nthreads;
+} opts_t;
+
+typedef struct {
+    uint8_t *status;   /* [n] */
+    double *t;         /* [n] hit distance from the camera (+inf if none) */
+    double *rgb;       /* [n][3] */
+    int32_t *probe;    /* [n] hit probe or -1 */
+    int32_t *texel;    /* [n] hit level-0 texel j*N+i or -1 */
+    int32_t *margin;   /* [n] bit mask */
+    int32_t *tests;    /* [n] distance/mip fetches of the hierarchical schedule */
+    int32_t *normals;  /* [n] normal fetches */
+    int32_t *flat_tests; /* [n] level-0 fetches of the flat march */
+    int32_t *rank;     /* [n] cell ordinal * 8 + cage rank of the resolving probe, -1 if none */
+    int32_t *taps;     /* [n][4] radiance tap texel indices (-1 for non-HIT) */
+    double *wts;       /* [n][4] bilinear weights */
+    double *score;     /* [n] min over decisions of gap / error scale (nullable) */
+} out_t;
+
+/* ------------------------------------------------------------------------------------
+ * Octahedral map (Overview, octahedral mapping): sphere -> octahedron |x|+|y|+|z| = 1
+ * -> unfold the lower four faces over the diagonals into the square [-1,1]^2.
+ * z is the fold axis; u follows x and v follows y.
+ * ------------------------------------------------------------------------------------ */
+static inline double sgnp(double a) { return a >= 0.0 ? 1.0 : -1.0; }
+
+void oracle_oct_encode(const double d[3], double uv[2]) {
+    double l1 = fabs(d[0]) + fabs(d[1]) + fabs(d[2]);
+    double px = d[0] / l1, py = d[1] / l1, pz = d[2] / l1;
+    if (pz >= 0.0) {
+        uv[0] = px;
+        uv[1] = py;
+    } else {
+        uv[0] = (1.0 - fabs(py)) * sgnp(px);
+        uv[1] = (1.0 - fabs(px)) * sgnp(py);
+    }
+}
+
+void oracle_oct_decode(const double uv[2], double d[3]) {
+    double x = uv[0], y = uv[1], z = 1.0 - fabs(uv[0]) - fabs(uv[1]);
+    if (z < 0.0) {
+        x = (1.0 - fabs(uv[1])) * sgnp(uv[0]);
+        y = (1.0 - fabs(uv[0])) * sgnp(uv[1]);
+    }
+    double l = sqrt(x * x + y * y + z * z);
+    d[0] = x / l;
+    d[1] = y / l;
+    d[2] = z / l;
+}
+
+/* IEEE binary16 -> double (exact) */
+static double half_to_double(uint16_t h) {
+    int s = (h >> 15) & 1, e = (h >> 10) & 31, m = h & 1023;
+    double v;
+    if (e == 0) v = ldexp((double)m, -24);
+    else if (e == 31) v = m ? NAN : INFINITY;
+    else v = ldexp((double)(m | 1024), e - 25);
+    return s ? -v : v;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Margin bookkeeping.  Each decisive comparison has a gap and a first-order error scale
+ * (how far a computation with relative rounding u could move the gap is about u*scale).
+ * The ray's score is the minimum of gap/scale over its decisions; a decision with
+ * gap <= delta*scale sets its bit in the ray's margin mask.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    int bits;
+    double score;
+    double delta;
+} mctx_t;
+
+static inline void decide(mctx_t *m, double gap, double scale, int bit) {
+    double ratio = fabs(gap) / scale;
+    if (!(ratio >= 0)) ratio = 0; /* NaN gap: treat as a tie */
+    if (ratio < m->score) m->score = ratio;
+    if (ratio <= m->delta) m->bits |= bit;
+}
+
+/* ------------------------------------------------------------------------------------
+ * One straight piece of the projected ray (RayMarching: projectRayOntoProbeData).
+ * Inside one octant (signs sx,sy,sz) the L1 norm is the linear form
+ * L(q) = sx qx + sy qy + sz qz, and the map coordinates are ratios of linear forms:
+ *   upper hemisphere: u = qx / L,                 v = qy / L
+ *   lower hemisphere: u = (qx + sx |qz|) / L,     v = (qy + sy |qz|) / L
+ * In texel units x = (u+1) N/2 = A(q)/L(q), y = B(q)/L(q) with A, B linear.  A texel
+ * boundary x = c is therefore the plane A(q) - c L(q) = 0 through the probe origin
+ * and the ray crosses it at t = (c L0 - A0) / (A1 - c L1), where F0 = F(X - O) and
+ * F1 = F(w).  x(t) is monotone on the piece; the boundary ahead in the direction of
+ * motion is reached in the future iff (A1 - c L1) has the sign of that direction.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    double ts, te, Ets, Ete;        /* interval and condition scale of its ends */
+    double A0, A1, B0, B1, L0, L1;  /* linear forms at the ray origin and along w */
+    int dx, dy;                     /* sign of dx/dt, dy/dt over the piece */
+    int ilo, ihi, jlo, jhi;         /* level-0 texel range of the octant's quadrant */
+} piece_t;
+
+typedef struct {
+    double Xp[3], w[3];  /* ray origin relative to the probe, unit direction */
+    double S;            /* magnitude scale of positions relative to the probe (|X - O|_1) */
+    mctx_t *m;
+} pray_t;
+
+static void piece_setup(piece_t *s, const pray_t *r, double ts, double te, double Ets, double Ete, int N) {
+    double tm = 0.5 * (ts + te);
+    double q[3] = {r->Xp[0] + tm * r->w[0], r->Xp[1] + tm * r->w[1], r->Xp[2] + tm * r->w[2]};
+    double sx = sgnp(q[0]), sy = sgnp(q[1]), sz = sgnp(q[2]);
+    double cL[3] = {sx, sy, sz};
+    double cU[3] = {1.0, 0.0, 0.0}, cV[3] = {0.0, 1.0, 0.0};
+    if (sz < 0) {
+        cU[2] = -sx; /* qx + sx|qz| with qz < 0 */
+        cV[2] = -sy;
+    }
+    double cA[3], cB[3];
+    for (int a = 0; a < 3; ++a) {
+        cA[a] = 0.5 * N * (cU[a] + cL[a]);
+        cB[a] = 0.5 * N * (cV[a] + cL[a]);
+    }
+    s->ts = ts; s->te = te; s->Ets = Ets; s->Ete = Ete;
+    s->A0 = s->A1 = s->B0 = s->B1 = s->L0 = s->L1 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        s->A0 += cA[a] * r->Xp[a]; s->A1 += cA[a] * r->w[a];
+        s->B0 += cB[a] * r->Xp[a]; s->B1 += cB[a] * r->w[a];
+        s->L0 += cL[a] * r->Xp[a]; s->L1 += cL[a] * r->w[a];
+    }
+    double gx = s->A1 * s->L0 - s->A0 * s->L1;
+    double gy = s->B1 * s->L0 - s->B0 * s->L1;
+    s->dx = gx > 0 ? 1 : (gx < 0 ? -1 : 0);
+    s->dy = gy > 0 ? 1 : (gy < 0 ? -1 : 0);
+    /* the octant (sx, sy, *) maps into the quadrant sign(u) = sx, sign(v) = sy */
+    s->ilo = sx > 0 ? N / 2 : 0;
+    s->ihi = sx > 0 ? N - 1 : N / 2 - 1;
+    s->jlo = sy > 0 ? N / 2 : 0;
+    s->jhi = sy > 0 ? N - 1 : N / 2 - 1;
+}
+
+/* crossing of the boundary x = c (P = A) or y = c (P = B) that lies ahead in direction
+ * dir; +inf if the ray never reaches it.  *E receives the condition scale of the result. */
+static double crossing(double c, int dir, double P0, double P1, double L0, double L1, double S, int N,
+                       double *E) {
+    double den = P1 - c * L1;
+    if (!(dir * den > 0)) { *E = 0; return INFINITY; }
+    double t = (c * L0 - P0) / den;
+    *E = (2.0 * fabs(c) + 2.0 * N) * (S + fabs(t)) / fabs(den);
+    return t;
+}
+
+static inline double rho_at(const pray_t *r, double t) {
+    double a = r->Xp[0] + t * r->w[0], b = r->Xp[1] + t * r->w[1], c = r->Xp[2] + t * r->w[2];
+    return sqrt(a * a + b * b + c * c);
+}
+
+/* |d rho / dt| at t */
+static inline double drho_at(const pray_t *r, double t) {
+    double a = r->Xp[0] + t * r->w[0], b = r->Xp[1] + t * r->w[1], c = r->Xp[2] + t * r->w[2];
+    double rr = sqrt(a * a + b * b + c * c);
+    return rr > 0 ? fabs(a * r->w[0] + b * r->w[1] + c * r->w[2]) / rr : 1.0;
+}
+
+typedef struct {
+    int fired;
+    int i, j;
+    double tin, tout, rin, Ein;
+} fire_t;
+
+/* next crossing candidates for texel (I,J) at level l (boundaries at multiples of 2^l);
+ * the edges of the octant's quadrant are never crossed inside a piece */
+static double next_x(const piece_t *s, int I, int l, int N, double S, double *E) {
+    *E = 0;
+    if (s->dx == 0) return INFINITY;
+    int c = (s->dx > 0 ? I + 1 : I) << l;
+    if (c <= s->ilo || c > s->ihi) return INFINITY;
+    return crossing((double)c, s->dx, s->A0, s->A1, s->L0, s->L1, S, N, E);
+}
+static double next_y(const piece_t *s, int J, int l, int N, double S, double *E) {
+    *E = 0;
+    if (s->dy == 0) return INFINITY;
+    int c = (s->dy > 0 ? J + 1 : J) << l;
+    if (c <= s->jlo || c > s->jhi) return INFINITY;
+    return crossing((double)c, s->dy, s->B0, s->B1, s->L0, s->L1, S, N, E);
+}
+
+static inline int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+/* would texel (i,j) fire on a vanishing span at radial distance rc?  (used to decide
+ * whether a near tie can change the outcome) */
+static int alt_fires(const float *D, int N, int i, int j, double rc, double tol) {
+    if (!D || i < 0 || j < 0 || i >= N || j >= N) return 0;
+    return (double)D[j * N + i] < rc + tol;
+}
+
+/* level-0 texel containing the ray point at the start of a piece.  If the start lies
+ * near a texel boundary and the texel on the other side would fire there, the ray is
+ * in margin. */
+static void start_texel(const piece_t *s, const pray_t *r, const float *D, int N, int *i, int *j) {
+    double L = s->L0 + s->L1 * s->ts;
+    if (!(L > 0.0)) { /* the piece starts at the probe origin itself */
+        double tm = 0.5 * (s->ts + s->te);
+        L = s->L0 + s->L1 * tm;
+        if (r->m) decide(r->m, 0.0, 1.0, MG_START);
+        if (!(L > 0.0)) { *i = s->ilo; *j = s->jlo; return; }
+        double x = (s->A0 + s->A1 * tm) / L, y = (s->B0 + s->B1 * tm) / L;
+        *i = clampi((int)floor(x), s->ilo, s->ihi);
+        *j = clampi((int)floor(y), s->jlo, s->jhi);
+        return;
+    }
+    double x = (s->A0 + s->A1 * s->ts) / L, y = (s->B0 + s->B1 * s->ts) / L;
+    *i = clampi((int)floor(x), s->ilo, s->ihi);
+    *j = clampi((int)floor(y), s->jlo, s->jhi);
+    if (!r->m) return;
+    /* error scale of x from the arithmetic and from the error of ts */
+    double dxdt = fabs(s->A1 * s->L0 - s->A0 * s->L1) / (L * L);
+    double dydt = fabs(s->B1 * s->L0 - s->B0 * s->L1) / (L * L);
+    double sx = 3.0 * N * (r->S + fabs(s->ts)) / L + dxdt * s->Ets;
+    double sy = 3.0 * N * (r->S + fabs(s->ts)) / L + dydt * s->Ets;
+    double cx = floor(x + 0.5), cy = floor(y + 0.5);
+    double rc = rho_at(r, s->ts);
+    double tol = 1e-3 * rc;
+    int ai = x >= cx ? (int)cx - 1 : (int)cx, aj = y >= cy ? (int)cy - 1 : (int)cy;
+    int nx = cx > s->ilo && cx <= s->ihi && fabs(x - cx) <= 1e3 * r->m->delta * sx;
+    int ny = cy > s->jlo && cy <= s->jhi && fabs(y - cy) <= 1e3 * r->m->delta * sy;
+    if (nx && (alt_fires(D, N, ai, *j, rc, tol) || (ny && alt_fires(D, N, ai, aj, rc, tol))))
+        decide(r->m, x - cx, sx, MG_START);
+    if (ny && (alt_fires(D, N, *i, aj, rc, tol) || (nx && alt_fires(D, N, ai, aj, rc, tol))))
+        decide(r->m, y - cy, sy, MG_START);
+}
+
+/* RayMarching over one piece at level 0 (the definition): first texel with
+ * r < max(rho_in, rho_out). */
+static void march_flat(const grid_t *g, int p, const pray_t *r, const piece_t *s, fire_t *f, int *ntests) {
+    const int N = g->N;
+    const float *D = g->dist + (int64_t)p * N * N;
+    int i, j;
+    start_texel(s, r, D, N, &i, &j);
+    double t = s->ts, Et = s->Ets, rc = rho_at(r, t);
+    double Ex, Ey;
+    double tx = next_x(s, i, 0, N, r->S, &Ex);
+    double ty = next_y(s, j, 0, N, r->S, &Ey);
+    f->fired = 0;
+    for (int it = 0; it < 8 * N + 16; ++it) {
+        double texit = s->te, Eexit = s->Ete;
+        if (tx < texit) { texit = tx; Eexit = Ex; }
+        if (ty < texit) { texit = ty; Eexit = Ey; }
+        if (texit < t) texit = t;
+        double re = rho_at(r, texit);
+        double m = rc > re ? rc : re;
+        double tmax = rc > re ? t : texit, Emax = rc > re ? Et : Eexit;
+        double rk = (double)D[j * N + i];
+        ++*ntests;
+        decide(r->m, rk - m, rk + r->S + fabs(tmax) + drho_at(r, tmax) * Emax, MG_FIRE);
+        if (rk < m) {
+            f->fired = 1; f->i = i; f->j = j;
+            f->tin = t; f->tout = texit; f->rin = rc; f->Ein = Et;
+            return;
+        }
+        /* near ties that decide the next texel matter only if a texel visited in the
+         * other order would fire on its vanishing span */
+        double tol = 1e-3 * re;
+        if (isfinite(tx) && isfinite(ty) && tx < s->te && ty < s->te &&
+            fabs(tx - ty) <= 1e3 * r->m->delta * (Ex + Ey) &&
+            (alt_fires(D, N, i + s->dx, j, re, tol) || alt_fires(D, N, i, j + s->dy, re, tol)))
+            decide(r->m, tx - ty, Ex + Ey, MG_DDA);
+        if (isfinite(tx) && fabs(tx - s->te) <= 1e3 * r->m->delta * (Ex + s->Ete) &&
+            alt_fires(D, N, i + s->dx, j, re, tol))
+            decide(r->m, tx - s->te, Ex + s->Ete, MG_DDA);
+        if (isfinite(ty) && fabs(ty - s->te) <= 1e3 * r->m->delta * (Ey + s->Ete) &&
+            alt_fires(D, N, i, j + s->dy, re, tol))
+            decide(r->m, ty - s->te, Ey + s->Ete, MG_DDA);
+        if (texit >= s->te) return;
+        int stepx = (tx == texit), stepy = (ty == texit);
+        t = texit; Et = Eexit; rc = re;
+        if (stepx) { i = clampi(i + s->dx, s->ilo, s->ihi); tx = next_x(s, i, 0, N, r->S, &Ex); }
+        if (stepy) { j = clampi(j + s->dy, s->jlo, s->jhi); ty = next_y(s, j, 0, N, r->S, &Ey); }
+    }
+}
+
+/* traceOneRaySegment with lowResolutionTracing / highResolutionTracing, generalised to a
+ * min pyramid: start at the top level, descend into a coarse texel that fires, step past
+ * one that does not (moving up again when the step leaves the parent), stop at the first
+ * level-0 fire.  Counts every distance/mip fetch. */
+static void march_hier(const grid_t *g, int p, const pray_t *r0, const piece_t *s, int top, fire_t *f,
+                       int *ntests) {
+    const int N = g->N;
+    pray_t rr = *r0;
+    rr.m = NULL; /* margins are judged on the flat march */
+    const pray_t *r = &rr;
+    int i0, j0;
+    start_texel(s, r, NULL, N, &i0, &j0);
+    int l = top;
+    int I = i0 >> l, J = j0 >> l;
+    double t = s->ts, Et = s->Ets, rc = rho_at(r, t);
+    double Ex, Ey;
+    double tx = next_x(s, I, l, N, r->S, &Ex);
+    double ty = next_y(s, J, l, N, r->S, &Ey);
+    f->fired = 0;
+    for (int it = 0; it < 64 * N + 64; ++it) {
+        double texit = s->te, Eexit = s->Ete;
+        if (tx < texit) { texit = tx; Eexit = Ex; }
+        if (ty < texit) { texit = ty; Eexit = Ey; }
+        if (texit < t) texit = t;
+        double re = rho_at(r, texit);
+        double m = rc > re ? rc : re;
+        int Nl = N >> l;
+        double M = l == 0 ? (double)g->dist[(int64_t)p * N * N + J * N + I]
+                          : (double)g->mips[g->mip_off[l] + (int64_t)p * Nl * Nl + J * Nl + I];
+        ++*ntests;
+        if (l == 0 ? (M < m) : (M < m * (1.0 + 1e-12))) {
+            if (l == 0) {
+                f->fired = 1; f->i = I; f->j = J;
+                f->tin = t; f->tout = texit; f->rin = rc; f->Ein = Et;
+                return;
+            }
+            /* descend into the child containing the ray point at t */
+            double L = s->L0 + s->L1 * t;
+            double x = (s->A0 + s->A1 * t) / L, y = (s->B0 + s->B1 * t) / L;
+            --l;
+            I = clampi((int)floor(x / (double)(1 << l)), 2 * I, 2 * I + 1);
+            J = clampi((int)floor(y / (double)(1 << l)), 2 * J, 2 * J + 1);
+            I = clampi(I, s->ilo >> l, s->ihi >> l);
+            J = clampi(J, s->jlo >> l, s->jhi >> l);
+            tx = next_x(s, I, l, N, r->S, &Ex);
+            ty = next_y(s, J, l, N, r->S, &Ey);
+            continue;
+        }
+        if (texit >= s->te) return;
+        int stepx = (tx == texit), stepy = (ty == texit);
+        int Io = I, Jo = J;
+        t = texit; Et = Eexit; rc = re;
+        if (stepx) I = clampi(I + s->dx, s->ilo >> l, s->ihi >> l);
+        if (stepy) J = clampi(J + s->dy, s->jlo >> l, s->jhi >> l);
+        while (l < top && ((I >> 1) != (Io >> 1) || (J >> 1) != (Jo >> 1))) {
+            I >>= 1; J >>= 1; Io >>= 1; Jo >>= 1; ++l;
+        }
+        tx = next_x(s, I, l, N, r->S, &Ex);
+        ty = next_y(s, J, l, N, r->S, &Ey);
+    }
+}
+
+/* bilinear taps at (u,v) with the octahedral border wrap (mirror across the edge) */
+static void bilinear_taps(double u, double v, int N, int idx[4], double wt[4]) {
+    double x = 0.5 * (u + 1.0) * N - 0.5, y = 0.5 * (v + 1.0) * N - 0.5;
+    double fi = floor(x), fj = floor(y);
+    double fx = x - fi, fy = y - fj;
+    int i0 = (int)fi, j0 = (int)fj;
+    for (int k = 0; k < 4; ++k) {
+        int di = k & 1, dj = k >> 1;
+        int i = i0 + di, j = j0 + dj;
+        if (i < 0) { i = 0; j = N - 1 - j; }
+        else if (i >= N) { i = N - 1; j = N - 1 - j; }
+        if (j < 0) { j = 0; i = N - 1 - i; }
+        else if (j >= N) { j = N - 1; i = N - 1 - i; }
+        i = clampi(i, 0, N - 1);
+        j = clampi(j, 0, N - 1);
+        idx[k] = j * N + i;
+        wt[k] = (di ? fx : 1.0 - fx) * (dj ? fy : 1.0 - fy);
+    }
+}
+
+typedef struct {
+    int status;
+    int texel;
+    double t;       /* hit distance along the ray */
+    double dirp[3]; /* direction from the probe to the hit point */
+    int tests, normals, flat_tests;
+} presult_t;
+
+/* traceOneProbe over [ta, tb] */
+static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const double X[3], const double w[3],
+                            double ta, double tb, double Eta, double Etb, mctx_t *mc, presult_t *res) {
+    const int N = g->N;
+    int pi = p % g->dims[0], pj = (p / g->dims[0]) % g->dims[1], pk = p / (g->dims[0] * g->dims[1]);
+    double O[3] = {g->origin[0] + pi * g->spacing[0], g->origin[1] + pj * g->spacing[1],
+                   g->origin[2] + pk * g->spacing[2]};
+    pray_t r;
+    r.m = mc;
+    r.S = 0;
+    /* probe positions are exact in the working precision (dyadic origin and spacing), so
+     * X - O carries only its own relative rounding: positions scale with |X - O|_1 */
+    for (int a = 0; a < 3; ++a) {
+        r.Xp[a] = X[a] - O[a];
+        r.w[a] = w[a];
+        r.S += fabs(r.Xp[a]);
+    }
+    memset(res, 0, sizeof(*res));
+    res->status = ST_MISS;
+    res->texel = -1;
+    double dist = sqrt(r.Xp[0] * r.Xp[0] + r.Xp[1] * r.Xp[1] + r.Xp[2] * r.Xp[2]);
+    double mins = g->spacing[0];
+    if (g->spacing[1] < mins) mins = g->spacing[1];
+    if (g->spacing[2] < mins) mins = g->spacing[2];
+    double eps = o->eye_eps_rel * mins;
+    if (dist > 0) decide(mc, dist - eps, eps / o->delta * 0.5 + 8.0 * r.S, MG_EYE);
+    if (dist <= eps) {
+        /* Eye aligned with the probe: every point of the ray maps to oct(w); O(1) lookup. */
+        double uv[2];
+        oracle_oct_encode(w, uv);
+        double x = 0.5 * (uv[0] + 1.0) * N, y = 0.5 * (uv[1] + 1.0) * N;
+        int i = clampi((int)floor(x), 0, N - 1), j = clampi((int)floor(y), 0, N - 1);
+        double cx = floor(x + 0.5), cy = floor(y + 0.5);
+        if (cx > 0 && cx < N) decide(mc, x - cx, 4.0 * N, MG_START);
+        if (cy > 0 && cy < N) decide(mc, y - cy, 4.0 * N, MG_START);
+        double rk = (double)g->dist[(int64_t)p * N * N + j * N + i];
+        res->tests = 1;
+        res->flat_tests = 1;
+        decide(mc, rk - ta, rk + r.S + Eta, MG_CELL);
+        decide(mc, rk - tb, rk + r.S + Etb, MG_CELL);
+        if (rk >= ta && rk <= tb) {
+            res->status = ST_HIT;
+            res->texel = j * N + i;
+            res->t = rk;
+            memcpy(res->dirp, w, sizeof(double) * 3);
+        }
+        return;
+    }
+    /* split [ta, tb] where a coordinate of X - O + t w changes sign: at most 4 pieces */
+    double cut[5], Ecut[5];
+    int nc = 0;
+    cut[nc] = ta; Ecut[nc] = Eta; ++nc;
+    for (int a = 0; a < 3; ++a) {
+        if (w[a] == 0.0) continue;
+        double tz = (O[a] - X[a]) / w[a];
+        double Ez = (fabs(X[a]) + fabs(O[a]) + fabs(tz)) / fabs(w[a]);
+        /* a cut on the cell's own boundary plane equals ta or tb exactly (same
+         * formula, same operands): that is structure, not a near tie */
+        if (tz != ta && tz > ta - 1.0 && tz < tb + 1.0) decide(mc, tz - ta, Ez + Eta, MG_OCTANT);
+        if (tz != tb && tz > ta - 1.0 && tz < tb + 1.0) decide(mc, tz - tb, Ez + Etb, MG_OCTANT);
+        if (tz > ta && tz < tb) {
+            cut[nc] = tz; Ecut[nc] = Ez; ++nc;
+        }
+    }
+    for (int a = 1; a < nc; ++a) /* sort the interior cuts */
+        for (int b = a + 1; b < nc; ++b)
+            if (cut[b] < cut[a]) {
+                double tt = cut[a]; cut[a] = cut[b]; cut[b] = tt;
+                tt = Ecut[a]; Ecut[a] = Ecut[b]; Ecut[b] = tt;
+            }
+    for (int a = 1; a + 1 < nc; ++a) decide(mc, cut[a + 1] - cut[a], Ecut[a] + Ecut[a + 1], MG_OCTANT);
+    cut[nc] = tb; Ecut[nc] = Etb;
+    int top = o->top_level < 0 || o->top_level > g->levels - 1 ? g->levels - 1 : o->top_level;
+    for (int sgi = 0; sgi < nc; ++sgi) {
+        piece_t s;
+        piece_setup(&s, &r, cut[sgi], cut[sgi + 1], Ecut[sgi], Ecut[sgi + 1], N);
+        fire_t ff = {0}, fh = {0};
+        march_flat(g, p, &r, &s, &ff, &res->flat_tests);
+        if (o->check_hier) {
+            march_hier(g, p, &r, &s, top, &fh, &res->tests);
+            if (fh.fired != ff.fired || (ff.fired && (fh.i != ff.i || fh.j != ff.j || fh.tin != ff.tin)))
+                mc->bits |= MG_HIER;
+        }
+        if (!ff.fired) continue;
+        /* highResolutionTracing: classify the first firing texel */
+        int k = ff.j * N + ff.i;
+        double rk = (double)g->dist[(int64_t)p * N * N + k];
+        res->texel = k;
+        double thr = rk * (1.0 + o->thickness_rel);
+        decide(mc, ff.rin - thr, rk + r.S + fabs(ff.tin) + drho_at(&r, ff.tin) * ff.Ein, MG_CLASS);
+        if (ff.rin > thr) {
+            res->status = ST_UNKNOWN; /* the ray entered the texel behind the stored surface */
+            return;
+        }
+        const uint16_t *nb = g->nrm + 2 * ((int64_t)p * N * N + k);
+        double nuv[2] = {half_to_double(nb[0]), half_to_double(nb[1])}, n[3];
+        oracle_oct_decode(nuv, n);
+        res->normals++;
+        double nd = n[0] * w[0] + n[1] * w[1] + n[2] * w[2];
+        decide(mc, nd, 4.0, MG_CLASS);
+        if (!(nd < 0.0)) {
+            res->status = ST_UNKNOWN;
+            return;
+        }
+        res->status = ST_HIT;
+        /* hit distance: entry point if already at/behind the surface, else where rho = r */
+        double th;
+        if (ff.rin >= rk) {
+            th = ff.tin;
+        } else {
+            double b = r.Xp[0] * w[0] + r.Xp[1] * w[1] + r.Xp[2] * w[2];
+            double pv[3] = {r.Xp[0] - b * w[0], r.Xp[1] - b * w[1], r.Xp[2] - b * w[2]};
+            double dp = sqrt(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
+            double disc = (rk - dp) * (rk + dp);
+            if (disc < 0) disc = 0;
+            double sq = sqrt(disc);
+            if (sq <= 1e-2 * rk) mc->bits |= MG_THIT;
+            if (b <= 0) th = -b + sq;
+            else th = (rk - dist) * (rk + dist) / (b + sq);
+        }
+        res->t = th;
+        for (int a = 0; a < 3; ++a) res->dirp[a] = r.Xp[a] + th * w[a];
+        return;
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * One camera ray: grid iterator over cells, closest-first cage probes, fall-through.
+ * ------------------------------------------------------------------------------------ */
+static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const double win[3], out_t *out,
+                      int64_t ri) {
+    double w[3];
+    double wl = sqrt(win[0] * win[0] + win[1] * win[1] + win[2] * win[2]);
+    for (int a = 0; a < 3; ++a) w[a] = win[a] / wl;
+    mctx_t mc;
+    mc.bits = 0;
+    mc.score = INFINITY;
+    mc.delta = o->delta;
+    int tests = 0, normals = 0, flat_tests = 0;
+    /* parameter range: until the ray leaves the scene box (slightly enlarged) */
+    double tfar = INFINITY, Efar = 0;
+    for (int a = 0; a < 3; ++a) {
+        double t = INFINITY;
+        if (w[a] > 0) t = (g->smax[a] - X[a]) / w[a];
+        else if (w[a] < 0) t = (g->smin[a] - X[a]) / w[a];
+        if (t < tfar) {
+            tfar = t;
+            Efar = (fabs(g->smax[a]) + fabs(g->smin[a]) + fabs(X[a]) + fabs(t)) / fabs(w[a]);
+        }
+    }
+    tfar *= 1.0 + 1e-4;
+    int any_unknown = 0;
+    int cell[3];
+    for (int a = 0; a < 3; ++a) {
+        double q = (X[a] - g->origin[a]) / g->spacing[a];
+        cell[a] = clampi((int)floor(q), 0, g->dims[a] - 2);
+        double c = floor(q + 0.5);
+        if (c >= 1 && c <= g->dims[a] - 2) decide(&mc, q - c, 4.0 * (fabs(X[a]) + fabs(g->origin[a])), MG_CELL);
+    }
+    double ta = 0.0, Eta = 0.0;
+    int mp = o->max_probes_per_cell < 1 || o->max_probes_per_cell > 8 ? 8 : o->max_probes_per_cell;
+    int ordinal = 0;
+    while (ta < tfar && tfar > 0) {
+        /* next interior grid plane along each axis */
+        double tn[3], En[3];
+        for (int a = 0; a < 3; ++a) {
+            tn[a] = INFINITY; En[a] = 0;
+            int pidx = -1;
+            if (w[a] > 0 && cell[a] + 1 <= g->dims[a] - 2) pidx = cell[a] + 1;
+            else if (w[a] < 0 && cell[a] >= 1) pidx = cell[a];
+            if (pidx >= 0) {
+                double plane = g->origin[a] + pidx * g->spacing[a];
+                tn[a] = (plane - X[a]) / w[a];
+                En[a] = (fabs(plane) + fabs(X[a]) + fabs(tn[a])) / fabs(w[a]);
+            }
+        }
+        double tb = tfar, Etb = Efar;
+        for (int a = 0; a < 3; ++a)
+            if (tn[a] < tb) { tb = tn[a]; Etb = En[a]; }
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(tn[a])) continue;
+            decide(&mc, tn[a] - tfar, En[a] + Efar, MG_CELL);
+            for (int b = a + 1; b < 3; ++b)
+                if (isfinite(tn[b])) decide(&mc, tn[a] - tn[b], En[a] + En[b], MG_CELL);
+        }
+        /* cage: the 8 corner probes, closest to the eye first, ties by corner code */
+        int code[8];
+        double dd[8];
+        for (int c = 0; c < 8; ++c) {
+            int ci = cell[0] + (c & 1), cj = cell[1] + ((c >> 1) & 1), ck = cell[2] + (c >> 2);
+            double d2 = 0;
+            double O[3] = {g->origin[0] + ci * g->spacing[0], g->origin[1] + cj * g->spacing[1],
+                           g->origin[2] + ck * g->spacing[2]};
+            for (int a = 0; a < 3; ++a) d2 += (O[a] - X[a]) * (O[a] - X[a]);
+            code[c] = c;
+            dd[c] = sqrt(d2);
+        }
+        for (int a = 1; a < 8; ++a) /* insertion sort, stable: ties keep corner-code order */
+            for (int b = a; b > 0 && dd[b] < dd[b - 1]; --b) {
+                double td = dd[b]; dd[b] = dd[b - 1]; dd[b - 1] = td;
+                int tc = code[b]; code[b] = code[b - 1]; code[b - 1] = tc;
+            }
+        for (int rk = 0; rk < mp; ++rk) {
+            int c = code[rk];
+            int p = (cell[0] + (c & 1)) +
+                    g->dims[0] * ((cell[1] + ((c >> 1) & 1)) + g->dims[1] * (cell[2] + (c >> 2)));
+            presult_t pr;
+            trace_one_probe(g, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
+            tests += pr.tests;
+            normals += pr.normals;
+            flat_tests += pr.flat_tests;
+            if (pr.status == ST_HIT) {
+                /* the order only mattered if the resolving probe nearly tied with a neighbour */
+                double cs = 8.0 * (dd[rk] + 4.0 * g->spacing[0]);
+                if (rk + 1 < mp) decide(&mc, dd[rk + 1] - dd[rk], cs, MG_CAGE);
+                if (rk > 0) decide(&mc, dd[rk] - dd[rk - 1], cs, MG_CAGE);
+                out->status[ri] = ST_HIT;
+                out->t[ri] = pr.t;
+                out->probe[ri] = p;
+                out->texel[ri] = pr.texel;
+                out->rank[ri] = ordinal * 8 + rk;
+                double uv[2];
+                oracle_oct_encode(pr.dirp, uv);
+                int idx[4];
+                double wt[4];
+                bilinear_taps(uv[0], uv[1], g->N, idx, wt);
+                const float *R = g->rad + (int64_t)p * g->N * g->N * 3;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double acc = 0;
+                    for (int k = 0; k < 4; ++k) acc += wt[k] * (double)R[3 * idx[k] + ch];
+                    out->rgb[3 * ri + ch] = acc;
+                }
+                if (out->taps)
+                    for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
+                goto done;
+            }
+            if (pr.status == ST_UNKNOWN) any_unknown = 1;
+        }
+        if (tb >= tfar) break;
+        for (int a = 0; a < 3; ++a)
+            if (tn[a] == tb) cell[a] += w[a] > 0 ? 1 : -1;
+        ta = tb; Eta = Etb;
+        ++ordinal;
+    }
+    out->status[ri] = (uint8_t)(any_unknown ? ST_UNKNOWN : ST_MISS);
+    out->t[ri] = INFINITY;
+    out->probe[ri] = -1;
+    out->texel[ri] = -1;
+    out->rank[ri] = -1;
+    for (int ch = 0; ch < 3; ++ch) out->rgb[3 * ri + ch] = o->background[ch];
+    if (out->taps)
+        for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = -1; out->wts[4 * ri + k] = 0; }
+done:
+    out->margin[ri] = mc.bits;
+    if (out->score) out->score[ri] = mc.score;
+    out->tests[ri] = tests;
+    out->normals[ri] = normals;
+    out->flat_tests[ri] = flat_tests;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Threaded driver over an array of rays.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    const grid_t *g;
+    const opts_t *o;
+    const double *orig, *dir;
+    int64_t n;
+    out_t *out;
+    atomic_long next;
+} job_t;
+
+static void *worker(void *arg) {
+    job_t *jb = (job_t *)arg;
+    for (;;) {
+        int64_t b = atomic_fetch_add(&jb->next, 256);
+        if (b >= jb->n) break;
+        int64_t e = b + 256 < jb->n ? b + 256 : jb->n;
+        for (int64_t i = b; i < e; ++i) trace_ray(jb->g, jb->o, jb->orig + 3 * i, jb->dir + 3 * i, jb->out, i);
+    }
+    return NULL;
+}
+
+int oracle_trace(const grid_t *g, const opts_t *o, int64_t n, const double *orig, const double *dir, out_t *out) {
+    int nt = o->nthreads < 1 ? 1 : (o->nthreads > 256 ? 256 : o->nthreads);
+    job_t jb;
+    jb.g = g; jb.o = o; jb.orig = orig; jb.dir = dir; jb.n = n; jb.out = out;
+    atomic_init(&jb.next, 0);
+    if (nt == 1) {
+        worker(&jb);
+        return 0;
+    }
+    pthread_t th[256];
+    for (int i = 0; i < nt; ++i) pthread_create(&th[i], NULL, worker, &jb);
+    for (int i = 0; i < nt; ++i) pthread_join(th[i], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Inspection hooks for the oracle's own tests.
+ * ------------------------------------------------------------------------------------ */
+
+/* Flat texel sequence of one probe over [ta, tb] (no stored distances involved):
+ * writes up to cap entries of (i, j, t_in, t_out, piece index); returns the count. */
+int oracle_texel_sequence(int N, const double Xp[3], const double win[3], double ta, double tb, int cap,
+                          int32_t *ij, double *tio, int32_t *piece) {
+    double w[3];
+    double wl = sqrt(win[0] * win[0] + win[1] * win[1] + win[2] * win[2]);
+    for (int a = 0; a < 3; ++a) w[a] = win[a] / wl;
+    pray_t r;
+    r.m = NULL;
+    r.S = 1;
+    memcpy(r.Xp, Xp, sizeof(double) * 3);
+    memcpy(r.w, w, sizeof(double) * 3);
+    double cut[5];
+    int nc = 0;
+    cut[nc++] = ta;
+    for (int a = 0; a < 3; ++a) {
+        if (w[a] == 0.0) continue;
+        double tz = -Xp[a] / w[a];
+        if (tz > ta && tz < tb) cut[nc++] = tz;
+    }
+    for (int a = 1; a < nc; ++a)
+        for (int b = a + 1; b < nc; ++b)
+            if (cut[b] < cut[a]) { double tt = cut[a]; cut[a] = cut[b]; cut[b] = tt; }
+    cut[nc] = tb;
+    int cnt = 0;
+    for (int sgi = 0; sgi < nc; ++sgi) {
+        piece_t s;
+        piece_setup(&s, &r, cut[sgi], cut[sgi + 1], 0, 0, N);
+        int i, j;
+        start_texel(&s, &r, NULL, N, &i, &j);
+        double t = s.ts, E;
+        double tx = next_x(&s, i, 0, N, r.S, &E);
+        double ty = next_y(&s, j, 0, N, r.S, &E);
+        for (int it = 0; it < 8 * N + 16; ++it) {
+            double texit = s.te;
+            if (tx < texit) texit = tx;
+            if (ty < texit) texit = ty;
+            if (texit < t) texit = t;
+            if (cnt < cap) {
+                ij[2 * cnt] = i; ij[2 * cnt + 1] = j;
+                tio[2 * cnt] = t; tio[2 * cnt + 1] = texit;
+                piece[cnt] = sgi;
+            }
+            ++cnt;
+            if (texit >= s.te) break;
+            int stepx = (tx == texit), stepy = (ty == texit);
+            t = texit;
+            if (stepx) { i = clampi(i + s.dx, s.ilo, s.ihi); tx = next_x(&s, i, 0, N, r.S, &E); }
+            if (stepy) { j = clampi(j + s.dy, s.jlo, s.jhi); ty = next_y(&s, j, 0, N, r.S, &E); }
+        }
+    }
+    return cnt;
+}
+
+void oracle_bilinear_taps(double u, double v, int N, int32_t idx[4], double wt[4]) {
+    int ii[4];
+    bilinear_taps(u, v, N, ii, wt);
+    for (int k = 0; k < 4; ++k) idx[k] = ii[k];
+}
+
+double oracle_half_to_double(uint16_t h) { return half_to_double(h); }

@@ -1,0 +1,360 @@
+"""Seeded synthetic inputs: rooms of boxes and spheres, probe bakes and camera views.
+
+This module only makes inputs.  It holds none of the probe-tracing method: the
+CPU oracle and the GPU library both consume what it produces and neither is
+imported here.  The paper's own inputs (FARO scans of a lab room, Data
+Collection / Data Processing sections) are not available, so these seeded
+synthetic rooms stand in for them.
+
+Scene recipe (all lengths relative to the probe spacing ``s``):
+
+* room = [0, dims*s]^3, six inward-facing walls with albedo U[0.1,0.9]^3;
+* probes at the vertices of a uniform grid, ``origin = s/2`` (probe (i,j,k) at
+  ``origin + (i,j,k)*s``), so every probe is strictly inside the room;
+* K objects, each a box (prob 1/2: centre uniform in the room, two half-extents
+  U[0.1,1.5]s and one, on a random axis, U[0.05,0.35]s) or a sphere (radius
+  U[0.1,0.4]s), albedo U[0.1,0.9]^3; an object closer than 0.05s to any probe
+  centre is redrawn;
+* cameras uniform in the room with clearance >= 0.1s from every surface,
+  yaw U[0,2pi), pitch U[-30,30] degrees, roll 0, vertical FOV 60 degrees.
+
+Random numbers come from PCG32 (O'Neill 2014, pcg-random.org, the
+``pcg32_random_r`` output function with the ``pcg32_srandom_r`` seeding).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+_MASK64 = (1 << 64) - 1
+
+
+class PCG32:
+    """PCG32 generator (XSH-RR output, 64-bit LCG state)."""
+
+    MULT = 6364136223846793005
+
+    def __init__(self, initstate: int, initseq: int = 54):
+        self.state = 0
+        self.inc = ((initseq << 1) | 1) & _MASK64
+        self.next_u32()
+        self.state = (self.state + initstate) & _MASK64
+        self.next_u32()
+
+    def next_u32(self) -> int:
+        old = self.state
+        self.state = (old * self.MULT + self.inc) & _MASK64
+        xorshifted = (((old >> 18) ^ old) >> 27) & 0xFFFFFFFF
+        rot = old >> 59
+        return ((xorshifted >> rot) | (xorshifted << ((-rot) & 31))) & 0xFFFFFFFF
+
+    def uniform(self, a: float = 0.0, b: float = 1.0) -> float:
+        return a + (b - a) * (self.next_u32() / 4294967296.0)
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Integer uniform on [lo, hi] inclusive."""
+        return lo + int(self.uniform() * (hi - lo + 1))
+
+    def normal(self) -> float:
+        u1 = self.uniform()
+        u2 = self.uniform()
+        u1 = max(u1, 1e-12)
+        return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+@dataclass
+class Scene:
+    dims: tuple            # probe grid dims (nx, ny, nz)
+    spacing: float
+    origin: float          # probe (0,0,0) sits at (origin, origin, origin)
+    room_max: np.ndarray   # (3,) room is [0, room_max]
+    wall_albedo: np.ndarray  # (6,3)
+    obj_type: np.ndarray   # (K,) int32, 0 box, 1 sphere
+    obj_param: np.ndarray  # (K,6) float64
+    obj_albedo: np.ndarray  # (K,3)
+    seed: int = 0
+
+    @property
+    def n_probes(self) -> int:
+        return int(self.dims[0] * self.dims[1] * self.dims[2])
+
+    def probe_positions(self) -> np.ndarray:
+        """(P,3) float64, probe index p = i + nx*(j + ny*k)."""
+        nx, ny, nz = self.dims
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        pos = np.stack([i, j, k], axis=-1).reshape(-1, 3).astype(np.float64)
+        return self.origin + pos * self.spacing
+
+    def with_albedos(self, seed: int) -> "Scene":
+        """Same geometry, albedos redrawn from ``seed`` (the differentiable target field)."""
+        rng = PCG32(seed)
+        walls = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(6)])
+        objs = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(len(self.obj_type))])
+        return Scene(self.dims, self.spacing, self.origin, self.room_max.copy(), walls,
+                     self.obj_type.copy(), self.obj_param.copy(), objs.reshape(-1, 3), seed)
+
+
+@dataclass
+class View:
+    pos: np.ndarray
+    right: np.ndarray
+    up: np.ndarray
+    fwd: np.ndarray
+    tan_half_fov_y: float
+    width: int
+    height: int
+
+    def as_tuple(self):
+        return (self.pos, self.right, self.up, self.fwd, self.tan_half_fov_y, self.width, self.height)
+
+
+def _box_point_dist(p, c, h):
+    q = np.abs(p - c) - h
+    outside = np.linalg.norm(np.maximum(q, 0.0))
+    return outside if outside > 0 else float(np.max(q))
+
+
+def make_scene(seed: int, dims, spacing: float, k_range) -> Scene:
+    """Draw a seeded room of boxes and spheres (module docstring recipe)."""
+    rng = PCG32(seed)
+    dims = tuple(int(d) for d in dims)
+    s = float(spacing)
+    origin = 0.5 * s
+    room_max = np.array(dims, dtype=np.float64) * s
+    walls = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(6)])
+    nx, ny, nz = dims
+    probes = [np.array([origin + i * s, origin + j * s, origin + k * s])
+              for k in range(nz) for j in range(ny) for i in range(nx)]
+    K = rng.randint(k_range[0], k_range[1])
+    types, params, albs = [], [], []
+    for _ in range(K):
+        for _attempt in range(2000):
+            is_box = rng.uniform() < 0.5
+            c = np.array([rng.uniform(0, room_max[a]) for a in range(3)])
+            if is_box:
+                h = np.array([rng.uniform(0.1, 1.5) * s, rng.uniform(0.1, 1.5) * s, 0.0])
+                thin = rng.randint(0, 2)
+                h[2] = rng.uniform(0.05, 0.35) * s
+                h[[2, thin]] = h[[thin, 2]]
+                ok = all(_box_point_dist(p, c, h) >= 0.05 * s for p in probes)
+                par = np.concatenate([c, h])
+            else:
+                r = rng.uniform(0.1, 0.4) * s
+                ok = all(np.linalg.norm(p - c) - r >= 0.05 * s for p in probes)
+                par = np.concatenate([c, [r, 0.0, 0.0]])
+            alb = [rng.uniform(0.1, 0.9) for _ in range(3)]
+            if ok:
+                types.append(0 if is_box else 1)
+                params.append(par)
+                albs.append(alb)
+                break
+    return Scene(dims, s, origin, room_max, walls, np.array(types, dtype=np.int32),
+                 np.array(params, dtype=np.float64).reshape(-1, 6),
+                 np.array(albs, dtype=np.float64).reshape(-1, 3), seed)
+
+
+def _camera_basis(yaw: float, pitch: float):
+    fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+    right = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
+    up = np.cross(right, fwd)
+    return right, up / np.linalg.norm(up), fwd
+
+
+def clearance(scene: Scene, pt) -> float:
+    lib = _load()
+    pt = np.ascontiguousarray(pt, dtype=np.float64)
+    return float(lib.synth_clearance(_dp(scene.room_max), int(len(scene.obj_type)),
+                                     _ip(scene.obj_type), _dp(scene.obj_param), _dp(pt)))
+
+
+def _draw_position(rng: PCG32, scene: Scene, min_clear: float):
+    for _ in range(100000):
+        p = np.array([rng.uniform(0, scene.room_max[a]) for a in range(3)])
+        if clearance(scene, p) >= min_clear:
+            return p
+    raise RuntimeError("could not place a camera")
+
+
+FOV_Y_DEG = 60.0
+
+
+def make_views(scene: Scene, seed: int, n_views: int, width=None, height=None, walk: bool = False,
+               w_range=(256, 1920), h_range=(256, 1080), step: float = 0.25):
+    """Seeded pinhole views.  ``walk`` makes a random walk (step 0.25, yaw += N(0,15deg)) with
+    uneven resolutions drawn from ``w_range`` x ``h_range``; otherwise independent poses at
+    ``width`` x ``height``."""
+    rng = PCG32(seed, initseq=0x5EED)
+    s = scene.spacing
+    clear = 0.1 * s
+    tanh = math.tan(math.radians(FOV_Y_DEG) / 2)
+    views = []
+    pos = _draw_position(rng, scene, clear)
+    yaw = rng.uniform(0, 2 * math.pi)
+    for v in range(n_views):
+        if v > 0:
+            if walk:
+                for _ in range(200):
+                    yaw_n = yaw + math.radians(15.0) * rng.normal()
+                    cand = pos + step * np.array([math.cos(yaw_n), math.sin(yaw_n), 0.0])
+                    if clearance(scene, cand) >= clear:
+                        pos, yaw = cand, yaw_n
+                        break
+                else:
+                    yaw = yaw + math.pi
+            else:
+                pos = _draw_position(rng, scene, clear)
+                yaw = rng.uniform(0, 2 * math.pi)
+        pitch = math.radians(rng.uniform(-30.0, 30.0))
+        if walk:
+            w = rng.randint(w_range[0], w_range[1])
+            h = rng.randint(h_range[0], h_range[1])
+        else:
+            w, h = int(width), int(height)
+        right, up, fwd = _camera_basis(yaw, pitch)
+        views.append(View(pos.copy(), right, up, fwd, tanh, w, h))
+    return views
+
+
+@dataclass
+class ProbeSet:
+    """Baked probe maps.  Texel (i, j) of an N x N map has linear index j*N + i."""
+    dims: tuple
+    origin: np.ndarray      # (3,) float32
+    spacing: np.ndarray     # (3,) float32
+    N: int
+    levels: int
+    scene_min: np.ndarray   # (3,) float32
+    scene_max: np.ndarray   # (3,) float32
+    distance: np.ndarray    # (P,N,N) float32
+    normal: np.ndarray      # (P,N,N,2) uint16, FP16 bits of the octahedral (u,v) of the normal
+    radiance: np.ndarray    # (P,N,N,3) uint16, FP16 bits of RGB
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_probes(self) -> int:
+        return int(self.distance.shape[0])
+
+    def radiance_f32(self) -> np.ndarray:
+        return self.radiance.view(np.float16).astype(np.float32)
+
+
+def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None) -> ProbeSet:
+    """Bake every probe of ``scene`` at N x N texels (centre-ray nearest surface)."""
+    lib = _load()
+    P = scene.n_probes
+    pos = np.ascontiguousarray(scene.probe_positions())
+    dist = np.empty((P, N, N), dtype=np.float32)
+    nrm = np.empty((P, N, N, 2), dtype=np.float32)
+    rad = np.empty((P, N, N, 3), dtype=np.float32)
+    sid = np.empty((P, N, N), dtype=np.int32)
+    nt = nthreads or min(16, os.cpu_count() or 1)
+    lib.synth_bake(_dp(scene.room_max), _dp(scene.wall_albedo), int(len(scene.obj_type)),
+                   _ip(scene.obj_type), _dp(scene.obj_param), _dp(scene.obj_albedo), P, _dp(pos), int(N),
+                   _fp(dist), _fp(nrm), _fp(rad), _ip(sid), int(nt))
+    f32 = lambda v: np.array(v, dtype=np.float32)
+    return ProbeSet(
+        dims=tuple(scene.dims), origin=f32([scene.origin] * 3), spacing=f32([scene.spacing] * 3), N=int(N),
+        levels=int(levels), scene_min=f32([0, 0, 0]), scene_max=f32(scene.room_max),
+        distance=dist, normal=nrm.astype(np.float16).view(np.uint16),
+        radiance=rad.astype(np.float16).view(np.uint16), extra=dict(surface_id=sid))
+
+
+def cast(scene: Scene, origins: np.ndarray, dirs: np.ndarray):
+    """Analytic nearest hit: returns t (inf if none), normal (n,3), albedo (n,3), surface id."""
+    lib = _load()
+    o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    t = np.empty(n, dtype=np.float64)
+    nn = np.empty((n, 3), dtype=np.float64)
+    alb = np.empty((n, 3), dtype=np.float64)
+    ids = np.empty(n, dtype=np.int32)
+    lib.synth_cast(_dp(scene.room_max), _dp(scene.wall_albedo), int(len(scene.obj_type)), _ip(scene.obj_type),
+                   _dp(scene.obj_param), _dp(scene.obj_albedo), ctypes.c_int64(n), _dp(o), _dp(d), _dp(t),
+                   _dp(nn), _dp(alb), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return t, nn, alb, ids
+
+
+# ---------------------------------------------------------------------------------------------
+# Workload presets: the five synthetic configurations.
+# ---------------------------------------------------------------------------------------------
+CONFIGS = {
+    "tiny": dict(seed=0, dims=(2, 2, 2), spacing=0.5, N=64, levels=4, k_range=(3, 6),
+                 views=dict(seed=100, n=1, width=128, height=128)),
+    "single": dict(seed=1, dims=(8, 8, 4), spacing=1.0, N=128, levels=5, k_range=(20, 40),
+                   views=dict(seed=101, n=1, width=1920, height=1080)),
+    "batched": dict(seed=1, dims=(8, 8, 4), spacing=1.0, N=128, levels=5, k_range=(20, 40),
+                    views=dict(seed=2, n=64, walk=True)),
+    "diff": dict(seed=3, dims=(16, 16, 8), spacing=1.0, N=256, levels=6, k_range=(20, 40),
+                 target_seed=4, views=dict(seed=103, n=32, width=512, height=512)),
+}
+
+
+def workload(name: str, N: int | None = None, levels: int | None = None, nthreads: int | None = None,
+             n_views: int | None = None, size=None):
+    """Build (scene, probes, views) for a named preset; N/levels/n_views/size override for tests."""
+    cfg = CONFIGS[name]
+    scene = make_scene(cfg["seed"], cfg["dims"], cfg["spacing"], cfg["k_range"])
+    probes = bake(scene, N or cfg["N"], levels or cfg["levels"], nthreads)
+    vc = cfg["views"]
+    nv = n_views or vc["n"]
+    if vc.get("walk"):
+        views = make_views(scene, vc["seed"], nv, walk=True)
+    else:
+        w, h = size if size else (vc["width"], vc["height"])
+        views = make_views(scene, vc["seed"], nv, w, h)
+    return scene, probes, views
+
+
+# ---------------------------------------------------------------------------------------------
+# native helper
+# ---------------------------------------------------------------------------------------------
+_lib = None
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def build_native(force: bool = True) -> str:
+    src = os.path.join(_HERE, "bake.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-pthread", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build_native(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        D = ctypes.POINTER(ctypes.c_double)
+        F = ctypes.POINTER(ctypes.c_float)
+        I = ctypes.POINTER(ctypes.c_int32)
+        lib.synth_bake.argtypes = [D, D, ctypes.c_int, I, D, D, ctypes.c_int, D, ctypes.c_int, F, F, F, I,
+                                   ctypes.c_int]
+        lib.synth_bake.restype = ctypes.c_int
+        lib.synth_cast.argtypes = [D, D, ctypes.c_int, I, D, D, ctypes.c_int64, D, D, D, D, D, I]
+        lib.synth_cast.restype = ctypes.c_int
+        lib.synth_clearance.argtypes = [D, ctypes.c_int, I, D, D]
+        lib.synth_clearance.restype = ctypes.c_double
+        _lib = lib
+    return _lib

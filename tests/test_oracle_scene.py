@@ -1,0 +1,137 @@
+"""Brute-force pin of the whole oracle against the analytic scene it was baked from.
+
+For a camera ray that the oracle resolves as HIT, the true surface point (analytic
+ray cast against the room's walls, boxes and spheres) must be within the error the
+probe representation allows: inside the firing texel the stored distance belongs to
+the texel's centre direction, so the stored sphere and the true surface plane differ
+radially by at most r*theta*tan(alpha) (theta = texel's angular diameter, alpha = angle
+between the surface normal and the probe's view direction), and an entry-point hit may
+sit behind the stored sphere by up to the thickness tau*r.  Measured along the camera
+ray that is  |T_oracle - T_true| <= r*(theta + tau) / |n . w|.  We allow a factor 1.5
+for curvature and second-order terms.
+
+Excluded (and counted), where the centre-ray bake cannot represent the surface:
+grazing rays (|n . w| < 0.1); hits within 2 texels of an edge between surfaces in the
+hit probe's map that is also a depth jump (> tau*r; the bake records which surface each
+texel saw); and camera rays that pass within two texel footprints of a silhouette in the
+camera's view (a ray through a point two footprints away from the true hit, across the
+ray, sees a different surface at a clearly different distance).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import workload
+
+
+def _texel_diameter(N):
+    """Max corner-to-corner angle of every texel (radians), [N*N]."""
+    e = np.linspace(-1, 1, N + 1)
+    corners = np.empty((N + 1, N + 1, 3))
+    for j in range(N + 1):
+        for i in range(N + 1):
+            corners[j, i] = oracle.oct_decode(np.array([e[i], e[j]]))
+    a = corners[:-1, :-1].reshape(-1, 3)
+    b = corners[1:, 1:].reshape(-1, 3)
+    c = corners[:-1, 1:].reshape(-1, 3)
+    d = corners[1:, :-1].reshape(-1, 3)
+    ang = lambda x, y: np.arccos(np.clip(np.sum(x * y, 1), -1, 1))
+    return np.maximum(ang(a, b), ang(c, d))
+
+
+def _discontinuity_mask(sid, dist, tau):
+    """Texels within 2 texels (Chebyshev) of a texel that sees another surface at a depth
+    differing by more than tau*r (a silhouette; creases between walls do not count)."""
+    P, N, _ = sid.shape
+    spad = np.pad(sid, ((0, 0), (2, 2), (2, 2)), mode="edge")
+    dpad = np.pad(dist, ((0, 0), (2, 2), (2, 2)), mode="edge")
+    bad = np.zeros(sid.shape, bool)
+    for dj in range(-2, 3):
+        for di in range(-2, 3):
+            s2 = spad[:, 2 + dj:2 + dj + N, 2 + di:2 + di + N]
+            d2 = dpad[:, 2 + dj:2 + dj + N, 2 + di:2 + di + N]
+            bad |= (s2 != sid) & (np.abs(d2 - dist) > tau * np.minimum(d2, dist))
+    return bad.reshape(P, -1)
+
+
+def _check(scene, probes, view, pixels=None):
+    g = oracle.Grid.from_probes(probes)
+    o, d = oracle.view_rays(*view.as_tuple(), pixels=pixels)
+    r = oracle.trace(g, o, d)
+    t_true, n_true, alb, ids = synth.cast(scene, o, d)
+    N = probes.N
+    tau = 8.0 / N
+    theta = _texel_diameter(N)
+    disc = _discontinuity_mask(probes.extra["surface_id"], probes.distance, tau)
+    hit = r["status"] == oracle.HIT
+    assert np.all(np.isfinite(t_true))  # the room is closed
+    cosw = np.abs(np.sum(n_true * d, 1))
+    p = np.where(hit, r["probe"], 0)
+    k = np.where(hit, r["texel"], 0)
+    rk = probes.distance[p].reshape(len(p), -1)[np.arange(len(p)), k].astype(np.float64)
+    excluded = hit & ((cosw < 0.1) | disc[p, k])
+    # camera-side surface edges: perturb the true hit across the ray by two footprints
+    cand = np.nonzero(hit & ~excluded)[0]
+    if len(cand):
+        P = o[cand] + t_true[cand, None] * d[cand]
+        rp = np.linalg.norm(P - np.stack([g.probe_position(q) for q in p[cand]]), axis=1)
+        F = 2.0 * theta[k[cand]] * np.maximum(rp, rk[cand])
+        dd = d[cand]
+        a = np.where(np.abs(dd[:, 0:1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+        e1 = np.cross(dd, a)
+        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+        e2 = np.cross(dd, e1)
+        near_edge = np.zeros(len(cand), bool)
+        for e in (e1, -e1, e2, -e2):
+            t2, _, _, ids2 = synth.cast(scene, o[cand], P + F[:, None] * e - o[cand])
+            jump = np.abs(t2 - t_true[cand]) > 4.0 * F / np.maximum(cosw[cand], 0.1)
+            near_edge |= (ids2 != ids[cand]) & jump
+        excluded[cand[near_edge]] = True
+    checked = hit & ~excluded
+    bound = 1.5 * rk * (theta[k] + tau) / np.maximum(cosw, 1e-12)
+    err = np.abs(r["t"] - t_true)
+    fails = checked & (err > bound)
+    return dict(n=len(hit), hit=hit.sum(), checked=checked.sum(), excluded=excluded.sum(), fails=fails.sum(),
+                rel_err=np.median(err[checked] / t_true[checked]) if checked.any() else 0.0, r=r)
+
+
+def test_tiny_room_against_analytic_scene(tiny):
+    scene, probes, views = tiny
+    s = _check(scene, probes, views[0])
+    assert s["hit"] > 0.95 * s["n"]          # closed room: nearly every ray is resolved
+    assert s["checked"] > 0.7 * s["n"]
+    assert s["fails"] == 0, s
+
+
+@pytest.mark.parametrize("name,size", [("single", (240, 135))])
+def test_room_against_analytic_scene(name, size):
+    scene, probes, views = workload(name, size=size)
+    s = _check(scene, probes, views[0])
+    assert s["hit"] > 0.9 * s["n"]
+    assert s["checked"] > 0.6 * s["n"]
+    assert s["fails"] == 0, {k: v for k, v in s.items() if k != "r"}
+
+
+def test_more_views_and_resolutions():
+    # other poses of the 1080p room at reduced map resolution (coarser texels, same bound)
+    scene, probes, views = workload("single", N=64, levels=4, size=(96, 64))
+    more = synth.make_views(scene, 777, 6, 96, 64)
+    for v in more:
+        s = _check(scene, probes, v)
+        assert s["hit"] > 0.85 * s["n"] and s["checked"] > 0.5 * s["n"]
+        assert s["fails"] == 0, {k: v for k, v in s.items() if k != "r"}
+
+
+def test_scene_complexity_does_not_change_fetch_counts_much():
+    # The paper reports render time independent of scene complexity; the oracle's
+    # per-ray fetch count for 3 vs 40 objects stays within a small factor.
+    counts = []
+    for k_range in ((3, 3), (40, 40)):
+        scene = synth.make_scene(21, (8, 8, 4), 1.0, k_range)
+        probes = synth.bake(scene, 64, 4)
+        v = synth.make_views(scene, 5, 1, 64, 48)[0]
+        g = oracle.Grid.from_probes(probes)
+        r = oracle.trace_view(g, v.as_tuple())
+        counts.append(r["tests"].mean())
+    assert max(counts) / min(counts) < 3.0
