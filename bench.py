@@ -1,0 +1,198 @@
+"""Benchmark: probe-grid ray tracing on one MI355X.
+
+One step = one full trace of the single-view workload: a seeded synthetic room of
+20-40 boxes and spheres baked into an 8x8x4 grid of probes with 128x128 octahedral maps
+(FP32 distance, FP16 normal and radiance, 5-level MIN pyramid), one 1920x1080 pinhole
+view.  value = rays traced per second (Mrays/s), inputs resident in HBM.
+
+Also reported: forward+backward Mrays/s on the same view (trace + radiance adjoint),
+the batched workload (64 views of uneven size in one persistent hipGraph launch) against
+64 plain launches, the roofline of the forward kernel and the CPU oracle timed on the
+host.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_FILE = os.path.join(ROOT, "tests", "golden", "algorithmic_bytes.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_fwd_1080p_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("probetrace.hip", "trace_device.h"):
+        with open(os.path.join(ROOT, "paper_2507_14624_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    s = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    if not m or not s or s.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(probes, view):
+    import numpy as np
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    g = oracle.Grid.from_probes(probes)
+    o, d = oracle.view_rays(*view.as_tuple())
+    t0 = time.perf_counter()
+    r = oracle.trace(g, o, d, nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = len(o)
+    return dict(value=n / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
+                sample=f"full {view.width}x{view.height} frame ({n} rays), double precision, {threads} threads, "
+                       f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="forward only (for profiling)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (scales HBM counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(rays shard by view with replicated probes; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_14624_amd as pt
+    import synth
+
+    torch.cuda.set_device(0)
+    print("[bench] building the single-view workload", file=sys.stderr, flush=True)
+    scene, probes, views = synth.workload("single")
+    view = views[0]
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    rays = view.width * view.height
+    va = pt.make_views([view])
+    opts = pt.trace_opts()
+    if not args.no_autotune:
+        opts = pt.probe_autotune(grid, rad, va, opts)
+    out = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"),
+           torch.empty(rays, dtype=torch.uint8, device="cuda"), torch.empty((rays, 2), dtype=torch.int32, device="cuda"))
+
+    def fwd():
+        pt.probe_trace(grid, rad, va, opts, out=out)
+
+    print("[bench] timing forward", file=sys.stderr, flush=True)
+    ms, wall = time_steps(fwd, args.steps, args.warmup, torch)
+    value = rays / (ms * 1e-3) / 1e6
+
+    with open(BYTES_FILE) as fh:
+        ab = json.load(fh)["single_1080p"]
+    achieved = ab["total_bytes"] / (ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    result = {
+        "metric": "Mrays/s probe trace (fwd, fwd+bwd) at 1080p; HBM GB/s vs peak; batched vs plain",
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single view 1920x1080; seeded room (seed 1) of 26 boxes/spheres; 8x8x4 probes, "
+                               "128x128 octahedral maps (FP32 distance, FP16 normal/radiance), 5-level min pyramid",
+                   "rays_per_step": rays, "tile": [opts.tile_w, opts.tile_h], "start_level": opts.start_level},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "kernel": "k_trace_view", "algorithmic_bytes_per_launch": ab["total_bytes"],
+                     "bytes_per_ray": ab["bytes_per_ray"]},
+    }
+    if not args.no_extras:
+        gsz = (probes.n_probes, probes.N, probes.N, 3)
+        grad = torch.zeros(gsz, device="cuda")
+        gout = torch.randn((rays, 3), device="cuda")
+
+        def fwd_bwd():
+            pt.probe_trace(grid, rad, va, opts, out=out)
+            grad.zero_()
+            pt.probe_trace_backward(grid, va, gout, grad, opts)
+
+        print("[bench] timing forward+backward", file=sys.stderr, flush=True)
+        ms_fb, _ = time_steps(fwd_bwd, max(3, args.steps // 2), 1, torch)
+        result["fwd_bwd"] = {"value": round(rays / (ms_fb * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                             "ms_per_step": round(ms_fb, 4)}
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        _, _, bviews = synth.workload("batched")
+        bva = pt.make_views(bviews)
+        brays = pt.n_rays(bviews)
+        bout = (torch.empty((brays, 3), device="cuda"), None, None, None)
+        gopts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level,
+                              flags=pt.PT_FLAG_GRAPH)
+        popts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level)
+        ms_g, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, gopts, out=bout), 3, 1, torch)
+        ms_p, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, popts, out=bout), 3, 1, torch)
+        result["batched"] = {"views": len(bviews), "rays": brays,
+                             "graph_persistent": {"value": round(brays / (ms_g * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                                                  "ms": round(ms_g, 3)},
+                             "plain_launches": {"value": round(brays / (ms_p * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                                                "ms": round(ms_p, 3)}}
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cb = cpu_baseline(probes, view)
+        result["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

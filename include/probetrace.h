@@ -1,0 +1,165 @@
+/*
+ * probetrace: ray tracing against a uniform grid of octahedral light-field probes on
+ * AMD Instinct MI355X (gfx950).  C ABI; every call is non-throwing and returns a
+ * pt_status.  All device pointers are HIP device memory of the current device; every
+ * call is asynchronous on the given stream (a hipStream_t passed as void*, NULL = the
+ * default stream) unless stated otherwise.  Host-side argument errors are reported
+ * before anything is enqueued.  pt_last_error() returns a thread-local message for the
+ * most recent failing call on this thread.
+ *
+ * The method (arXiv 2507.14624, "Real-Time Scene Reconstruction using Light Field
+ * Probes"):
+ *   - each probe stores octahedral maps of radial distance and normal (Overview;
+ *     Implementation Details > Probe Data Generation) plus radiance, and a chain of
+ *     lower-resolution distance maps derived from the full-resolution one, here a 2x2
+ *     MIN pyramid (so the hierarchy only skips space, never changes a result);
+ *   - a camera ray walks the grid cells it crosses (Ray Trace Using Multiple Probes >
+ *     Grid Iterator) and, in each cell, tries the cell's 8 corner probes closest to the
+ *     eye first, falling through on MISS and on UNKNOWN (Less Than 8 Probes);
+ *   - one probe: if the eye sits at the probe, an O(1) lookup of the map at oct(w)
+ *     (Eye Aligned with a Probe, appendix traceOneProbe); otherwise the ray is split
+ *     into at most four straight pieces of the octahedral map and each is marched,
+ *     coarse levels first (appendix traceOneRaySegment, lowResolutionTracing,
+ *     highResolutionTracing; Ray Tracing Using One Probe);
+ *   - the first level-0 texel whose stored distance r is below the ray's distance from
+ *     the probe inside that texel decides: UNKNOWN if the ray entered the texel already
+ *     behind the stored surface by more than the thickness (the ray "shoots from below
+ *     the surface"), else HIT if stored normal . w < 0, else UNKNOWN; no such texel:
+ *     MISS;
+ *   - a HIT returns the probe's radiance in the direction of the hit point (the
+ *     L_o(X,w1) = L_p(w2) identity of the Overview), bilinearly filtered with the
+ *     octahedral border wrap.
+ *
+ * Conventions
+ *   - octahedral map: z is the fold axis, u follows x and v follows y; texel (i, j) of
+ *     an N x N map covers u in [-1+2i/N, -1+2(i+1)/N] (likewise v, j) and has linear
+ *     index j*N + i in every caller-visible array;
+ *   - probe (i, j, k) has index p = i + nx*(j + ny*k) and sits at origin + (i,j,k)*spacing;
+ *   - FP16 arrays hold IEEE binary16 bit patterns (uint16_t).
+ */
+#ifndef PROBETRACE_H
+#define PROBETRACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PT_OK = 0,
+    PT_ERR_INVALID_ARGUMENT = 1, /* a host-side check failed; nothing was enqueued */
+    PT_ERR_OUT_OF_MEMORY = 2,    /* a library allocation failed */
+    PT_ERR_HIP = 3,              /* a HIP call failed (message names it) */
+    PT_ERR_UNSUPPORTED = 4       /* a valid request this build does not support */
+} pt_status;
+
+/* per-ray classification (Ray Tracing Using One Probe): the final status of a camera ray
+ * is HIT if any probe hit, else UNKNOWN if any probe answered UNKNOWN, else MISS */
+typedef enum { PT_MISS = 0, PT_HIT = 1, PT_UNKNOWN = 2 } pt_ray_status;
+
+typedef struct pt_grid pt_grid; /* opaque: the probe geometry resident on one device */
+
+/* Uniform probe grid (Figure 3(a): probes at the vertices of a uniform 3D grid). */
+typedef struct {
+    int32_t dims[3];      /* probes per axis, each >= 2 */
+    float origin[3];      /* position of probe (0,0,0) */
+    float spacing[3];     /* > 0; probe (i,j,k) at origin + (i,j,k)*spacing */
+    int32_t map_res;      /* N: power of two, 8 <= N <= 4096 */
+    int32_t mip_levels;   /* L >= 1 levels including the full map; N >> (L-1) >= 2 */
+    float scene_min[3];   /* rays end where they leave this box (enlarged by 1e-4 of the */
+    float scene_max[3];   /* exit distance) */
+} pt_grid_desc;
+
+/* Pinhole camera: pixel (x, y), row 0 at the top, has direction
+ *   normalize(fwd + ((2(x+1/2)/W - 1) (W/H) tan_half_fov_y) right
+ *                 + ((1 - 2(y+1/2)/H) tan_half_fov_y) up)
+ * from pos.  Rays of one view are stored row-major (y*W + x). */
+typedef struct {
+    float pos[3], right[3], up[3], fwd[3];
+    float tan_half_fov_y;
+    int32_t width, height; /* >= 1 */
+} pt_view;
+
+/* Algorithm constants and tuning knobs.  pt_trace_opts_default() fills the defaults. */
+typedef struct {
+    float thickness_rel;          /* tau of the shadow-entry test, relative to the stored
+                                     distance; <= 0 selects 8/N; +INF = no shadow-entry test */
+    float eye_eps_rel;            /* eye at a probe when |X - O| <= eye_eps_rel * min spacing;
+                                     <= 0 selects 1e-6 */
+    float background[3];          /* rgb written for rays that are not HIT */
+    int32_t max_probes_per_cell;  /* probes tried per cell, 1..8; <= 0 selects 8 */
+    int32_t tile_w, tile_h;       /* pixels per wavefront tile, tile_w * tile_h = 64; 0 = 8x8 */
+    int32_t start_level;          /* pyramid level the march starts at; < 0 = coarsest */
+    uint32_t flags;               /* PT_FLAG_* */
+} pt_trace_opts;
+
+#define PT_FLAG_PERSISTENT 1u /* one persistent launch over a device tile queue */
+#define PT_FLAG_GRAPH 2u      /* capture the launch in a hipGraph and replay it on `stream`
+                                 (implies PERSISTENT); the graph is cached per grid and
+                                 rebuilt when views, pointers or options change */
+
+void pt_trace_opts_default(pt_trace_opts *opts);
+
+/* Create the device-resident probe grid.
+ *   distance_dev    [P][N][N] FP32 radial distance from the probe (NaN = no data: never
+ *                   fires; 0 everywhere = a probe that answers UNKNOWN everywhere)
+ *   normal_oct_dev  [P][N][N][2] FP16 bits: octahedral (u, v) of the stored normal
+ * The library copies both into its own layout and builds the MIN pyramid on `stream`; the
+ * caller keeps its arrays alive until `stream` has passed this call.  *out receives the
+ * grid (NULL on failure).  Errors: INVALID_ARGUMENT (bad desc or NULL pointer),
+ * OUT_OF_MEMORY, HIP. */
+pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev, const uint16_t *normal_oct_dev,
+                            void *stream, pt_grid **out);
+
+/* Free a grid (synchronises the device first).  NULL is ignored. */
+void probe_grid_destroy(pt_grid *grid);
+
+/* Copy pyramid level `level` (0 = the full map) of every probe into out_dev,
+ * [P][N>>level][N>>level] FP32 row-major.  For inspection and tests. */
+pt_status probe_grid_read_level(const pt_grid *grid, int32_t level, float *out_dev, void *stream);
+
+/* Trace every pixel of n_views views (Overview; Ray Tracing Using One Probe / Multiple
+ * Probes).  Outputs are concatenated by view in order, row-major inside a view.
+ *   radiance_dev  [P][N][N][3] FP16 bits, caller-owned, read only
+ *   rgb_dev       [rays][3] FP32: radiance of HIT rays, opts->background otherwise
+ *   t_dev         [rays] FP32 hit distance from the camera, +INF if not HIT (nullable)
+ *   status_dev    [rays] uint8 pt_ray_status (nullable)
+ *   hit_dev       [rays][2] int32 (probe, level-0 texel j*N+i) of the HIT, (-1,-1)
+ *                 otherwise (nullable)
+ * opts may be NULL (defaults).  Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host, int32_t n_views,
+                      float *rgb_dev, float *t_dev, uint8_t *status_dev, int32_t *hit_dev, const pt_trace_opts *opts,
+                      void *stream);
+
+/* Trace arbitrary rays: origins_dev and dirs_dev are [n][3] FP32 (directions need not be
+ * unit length; zero-length directions give MISS).  Outputs as for probe_trace. */
+pt_status probe_trace_rays(const pt_grid *grid, const uint16_t *radiance_dev, const float *origins_dev,
+                           const float *dirs_dev, int64_t n, float *rgb_dev, float *t_dev, uint8_t *status_dev,
+                           int32_t *hit_dev, const pt_trace_opts *opts, void *stream);
+
+/* Adjoint of probe_trace with respect to the radiance texels, the hit test held fixed
+ * (it never reads radiance).  Recomputes the trace, then for every HIT ray adds
+ * w_tap * grad_rgb[c] to grad_radiance_dev[p][tap][c] for its 4 bilinear taps.
+ *   grad_rgb_dev       [rays][3] FP32, same ray order as probe_trace
+ *   grad_radiance_dev  [P][N][N][3] FP32, ACCUMULATED into (+=); caller zeroes it
+ * Summation order depends on scheduling (FP32 atomics after an in-wavefront reduction).
+ * Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, int32_t n_views,
+                               const float *grad_rgb_dev, float *grad_radiance_dev, const pt_trace_opts *opts,
+                               void *stream);
+
+/* Choose tile shape and pyramid start level for these views by timing candidate
+ * launches on `stream` (synchronous; writes into the outputs, which must hold the views'
+ * rays).  Results do not depend on the choice.  *opts is read for the algorithm constants
+ * and receives tile_w, tile_h, start_level.  Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_autotune(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
+                         int32_t n_views, float *rgb_dev, pt_trace_opts *opts, void *stream);
+
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBETRACE_H */

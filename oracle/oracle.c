@@ -563,6 +563,8 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
         double th;
         if (ff.rin >= rk) {
             th = ff.tin;
+            /* the entry crossing's condition scale decides how well t is known */
+            if (1e-2 * ff.Ein > fabs(th)) mc->bits |= MG_THIT;
         } else {
             double b = r.Xp[0] * w[0] + r.Xp[1] * w[1] + r.Xp[2] * w[2];
             double pv[3] = {r.Xp[0] - b * w[0], r.Xp[1] - b * w[1], r.Xp[2] - b * w[2]};

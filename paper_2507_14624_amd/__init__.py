@@ -1,0 +1,276 @@
+"""Probe-grid ray tracing on MI355X: thin Python binding over libprobetrace.so.
+
+Every step of the trace runs in the HIP library (``csrc/``); this module only marshals
+arguments (torch device tensors as raw pointers, the current HIP stream) into the C ABI
+declared in ``include/probetrace.h``.  There is no fallback: if the library is missing
+or no GPU is visible, the calls raise.
+
+Method: arXiv 2507.14624 (see the header for the passages each entry point follows).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprobetrace.so")
+
+PT_MISS, PT_HIT, PT_UNKNOWN = 0, 1, 2
+PT_FLAG_PERSISTENT = 1
+PT_FLAG_GRAPH = 2
+
+EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
+            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_autotune", "pt_last_error")
+
+
+class PtGridDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3),
+                ("map_res", ctypes.c_int32), ("mip_levels", ctypes.c_int32), ("scene_min", ctypes.c_float * 3),
+                ("scene_max", ctypes.c_float * 3)]
+
+
+class PtView(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("right", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fwd", ctypes.c_float * 3), ("tan_half_fov_y", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class PtTraceOpts(ctypes.Structure):
+    _fields_ = [("thickness_rel", ctypes.c_float), ("eye_eps_rel", ctypes.c_float),
+                ("background", ctypes.c_float * 3), ("max_probes_per_cell", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("start_level", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class ProbeTraceError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libprobetrace.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.pt_trace_opts_default.argtypes = [ctypes.POINTER(PtTraceOpts)]
+    lib.pt_trace_opts_default.restype = None
+    lib.probe_grid_create.argtypes = [ctypes.POINTER(PtGridDesc), vp, vp, vp, ctypes.POINTER(vp)]
+    lib.probe_grid_destroy.argtypes = [vp]
+    lib.probe_grid_destroy.restype = None
+    lib.probe_grid_read_level.argtypes = [vp, i32, vp, vp]
+    lib.probe_trace.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_trace_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_trace_backward.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_autotune.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, ctypes.POINTER(PtTraceOpts), vp]
+    for name in ("probe_grid_create", "probe_grid_read_level", "probe_trace", "probe_trace_rays",
+                 "probe_trace_backward", "probe_autotune"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.pt_last_error.argtypes = []
+    lib.pt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = _lib.pt_last_error().decode(errors="replace")
+        raise ProbeTraceError(f"probetrace status {status}: {msg}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ProbeTraceError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ProbeTraceError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ProbeTraceError(f"{name} must be contiguous")
+    return t
+
+
+def trace_opts(thickness_rel=0.0, eye_eps_rel=0.0, background=(0.0, 0.0, 0.0), max_probes_per_cell=8,
+               tile=(8, 8), start_level=-1, flags=0) -> PtTraceOpts:
+    o = PtTraceOpts()
+    load_library().pt_trace_opts_default(ctypes.byref(o))
+    o.thickness_rel = float(thickness_rel)
+    o.eye_eps_rel = float(eye_eps_rel)
+    o.background[:] = [float(c) for c in background]
+    o.max_probes_per_cell = int(max_probes_per_cell)
+    o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+    o.start_level = int(start_level)
+    o.flags = int(flags)
+    return o
+
+
+def make_views(views) -> ctypes.Array:
+    """Views as a ctypes array; each view has pos/right/up/fwd/tan_half_fov_y/width/height."""
+    arr = (PtView * len(views))()
+    for a, v in zip(arr, views):
+        a.pos[:] = [float(c) for c in v.pos]
+        a.right[:] = [float(c) for c in v.right]
+        a.up[:] = [float(c) for c in v.up]
+        a.fwd[:] = [float(c) for c in v.fwd]
+        a.tan_half_fov_y = float(v.tan_half_fov_y)
+        a.width = int(v.width)
+        a.height = int(v.height)
+    return arr
+
+
+def n_rays(views) -> int:
+    return int(sum(int(v.width) * int(v.height) for v in views))
+
+
+class ProbeGrid:
+    """Device-resident probe geometry (probe_grid_create / probe_grid_destroy)."""
+
+    def __init__(self, dims, origin, spacing, map_res, mip_levels, scene_min, scene_max, distance, normal_half,
+                 stream=None):
+        lib = load_library()
+        distance = _dev_tensor(distance, torch.float32, "distance")
+        normal_half = _dev_tensor(normal_half, torch.float16, "normal (FP16 octahedral u, v)")
+        d = PtGridDesc()
+        d.dims[:] = [int(x) for x in dims]
+        d.origin[:] = [float(x) for x in origin]
+        d.spacing[:] = [float(x) for x in spacing]
+        d.map_res = int(map_res)
+        d.mip_levels = int(mip_levels)
+        d.scene_min[:] = [float(x) for x in scene_min]
+        d.scene_max[:] = [float(x) for x in scene_max]
+        P = d.dims[0] * d.dims[1] * d.dims[2]
+        N = d.map_res
+        if tuple(distance.shape) != (P, N, N) or tuple(normal_half.shape) != (P, N, N, 2):
+            raise ProbeTraceError(f"expected distance [{P},{N},{N}] and normal [{P},{N},{N},2]")
+        self.handle = ctypes.c_void_p()
+        self.desc = d
+        self.P, self.N, self.levels = P, N, d.mip_levels
+        self.dims = tuple(d.dims)
+        self.device = distance.device
+        _check(lib.probe_grid_create(ctypes.byref(d), _ptr(distance), _ptr(normal_half), _stream(stream),
+                                     ctypes.byref(self.handle)))
+        # the library copies on the stream: keep the inputs alive until it has run
+        (stream or torch.cuda.current_stream()).synchronize()
+
+    @classmethod
+    def from_probes(cls, probes, device="cuda"):
+        """From a baked probe set (numpy arrays, see synth.ProbeSet)."""
+        import numpy as np
+        dist = torch.from_numpy(np.ascontiguousarray(probes.distance)).to(device)
+        nrm = torch.from_numpy(np.ascontiguousarray(probes.normal).view(np.float16)).to(device)
+        return cls(probes.dims, probes.origin, probes.spacing, probes.N, probes.levels, probes.scene_min,
+                   probes.scene_max, dist, nrm)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load_library().probe_grid_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def read_level(self, level: int, stream=None) -> torch.Tensor:
+        n = self.N >> level
+        out = torch.empty((self.P, n, n), dtype=torch.float32, device=self.device)
+        _check(load_library().probe_grid_read_level(self.handle, int(level), _ptr(out), _stream(stream)))
+        return out
+
+
+def _alloc_outputs(rays, device, want_t=True, want_status=True, want_hit=True):
+    rgb = torch.empty((rays, 3), dtype=torch.float32, device=device)
+    t = torch.empty(rays, dtype=torch.float32, device=device) if want_t else None
+    st = torch.empty(rays, dtype=torch.uint8, device=device) if want_status else None
+    hit = torch.empty((rays, 2), dtype=torch.int32, device=device) if want_hit else None
+    return rgb, t, st, hit
+
+
+def probe_trace(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None = None, out=None, stream=None,
+                want_t=True, want_status=True, want_hit=True):
+    """Trace every pixel of ``views``; returns dict(rgb, t, status, hit) of device tensors."""
+    lib = load_library()
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    rgb, t, st, hit = out if out is not None else _alloc_outputs(rays, radiance_half.device, want_t, want_status,
+                                                                  want_hit)
+    _check(lib.probe_trace(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), _ptr(t), _ptr(st), _ptr(hit),
+                           ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return dict(rgb=rgb, t=t, status=st, hit=hit)
+
+
+def probe_trace_rays(grid: ProbeGrid, radiance_half, origins, dirs, opts: PtTraceOpts | None = None, stream=None):
+    lib = load_library()
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    origins = _dev_tensor(origins, torch.float32, "origins")
+    dirs = _dev_tensor(dirs, torch.float32, "dirs")
+    n = origins.shape[0]
+    rgb, t, st, hit = _alloc_outputs(n, origins.device)
+    _check(lib.probe_trace_rays(grid.handle, _ptr(radiance_half), _ptr(origins), _ptr(dirs), int(n), _ptr(rgb),
+                                _ptr(t), _ptr(st), _ptr(hit), ctypes.byref(opts) if opts is not None else None,
+                                _stream(stream)))
+    return dict(rgb=rgb, t=t, status=st, hit=hit)
+
+
+def probe_trace_backward(grid: ProbeGrid, views, grad_rgb, grad_radiance, opts: PtTraceOpts | None = None,
+                         stream=None):
+    """Accumulate (+=) the radiance gradient of sum(grad_rgb * rgb) into grad_radiance [P,N,N,3] FP32."""
+    lib = load_library()
+    grad_rgb = _dev_tensor(grad_rgb, torch.float32, "grad_rgb")
+    grad_radiance = _dev_tensor(grad_radiance, torch.float32, "grad_radiance")
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib.probe_trace_backward(grid.handle, va, len(va), _ptr(grad_rgb), _ptr(grad_radiance),
+                                    ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return grad_radiance
+
+
+def probe_autotune(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None = None, stream=None):
+    """Time candidate tile shapes and start levels; returns the tuned options."""
+    lib = load_library()
+    opts = opts if opts is not None else trace_opts()
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    rgb = torch.empty((rays, 3), dtype=torch.float32, device=radiance_half.device)
+    _check(lib.probe_autotune(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), ctypes.byref(opts),
+                              _stream(stream)))
+    return opts
+
+
+class ProbeTraceFn(torch.autograd.Function):
+    """rgb = trace(radiance) with the hit test held fixed.
+
+    forward: the FP32 master radiance is rounded to the FP16 storage the trace reads;
+    backward: probe_trace_backward into a zeroed FP32 buffer, passed straight through the
+    FP16 rounding to the master."""
+
+    @staticmethod
+    def forward(ctx, master, grid, views, opts=None):
+        storage = master.detach().to(torch.float16).contiguous()
+        va = views if isinstance(views, ctypes.Array) else make_views(views)
+        res = probe_trace(grid, storage, va, opts, want_t=False, want_status=False, want_hit=False)
+        ctx.grid, ctx.views, ctx.opts = grid, va, opts
+        ctx.shape = master.shape
+        return res["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        g = torch.zeros(ctx.shape, dtype=torch.float32, device=grad_rgb.device)
+        probe_trace_backward(ctx.grid, ctx.views, grad_rgb.contiguous().float(), g, ctx.opts)
+        return g, None, None, None

@@ -1,0 +1,644 @@
+// probetrace: C-ABI library for probe-grid ray tracing on MI355X (gfx950).
+// Kernels: pyramid build, per-view trace, arbitrary-ray trace, persistent multi-view
+// trace over a device tile queue (optionally captured in a hipGraph), and the radiance
+// adjoint.  The contract is in include/probetrace.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "probetrace.h"
+#include "trace_device.h"
+
+using namespace pt;
+
+// ------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static pt_status fail(pt_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(PT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+extern "C" const char *pt_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------------------------
+// grid object
+// ------------------------------------------------------------------------------------
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<unsigned char> key;
+    ViewDev *views_dev = nullptr;
+    int cap = 0;
+    hipStream_t capture = nullptr;  // private stream the graph is captured on
+};
+
+struct pt_grid {
+    pt_grid_desc desc;
+    int device = 0;
+    int P = 0, N = 0, L = 0;
+    int64_t stride = 0;
+    float *pyr = nullptr;
+    uint32_t *nrm = nullptr;
+    // multi-view launches: view table and tile counter
+    ViewDev *views_dev = nullptr;
+    ViewDev *views_host = nullptr;  // pinned staging
+    int views_cap = 0;
+    hipEvent_t staging_free = nullptr;
+    int *counter = nullptr;
+    GraphCache graph;
+    int num_cus = 256;
+};
+
+// ------------------------------------------------------------------------------------
+// pyramid build
+// ------------------------------------------------------------------------------------
+__global__ void k_pack(const float *__restrict__ dist, const uint16_t *__restrict__ nrm_in, float *__restrict__ pyr,
+                       uint32_t *__restrict__ nrm, int N, int64_t stride, int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int64_t NN = (int64_t)N * N;
+    int64_t p = g / NN, k = g % NN;
+    pyr[p * stride + k] = dist[g];
+    uint32_t lo = nrm_in[2 * g], hi = nrm_in[2 * g + 1];
+    nrm[g] = lo | (hi << 16);
+}
+
+// level l texel = min of its 4 children at level l-1 (fminf: a NaN child is ignored)
+__global__ void k_mip(float *__restrict__ pyr, int N, int l, int64_t stride, int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int nl = N >> l, nc = N >> (l - 1);
+    int64_t per = (int64_t)nl * nl;
+    int64_t p = g / per;
+    int k = (int)(g % per);
+    int i = k % nl, j = k / nl;
+    float *blk = pyr + p * stride;
+    const float *c = blk + level_offset(N, l - 1);
+    float a = c[(2 * j) * nc + 2 * i], b = c[(2 * j) * nc + 2 * i + 1];
+    float d = c[(2 * j + 1) * nc + 2 * i], e = c[(2 * j + 1) * nc + 2 * i + 1];
+    blk[level_offset(N, l) + j * nl + i] = fminf(fminf(a, b), fminf(d, e));
+}
+
+__global__ void k_read_level(const float *__restrict__ pyr, float *__restrict__ out, int N, int l, int64_t stride,
+                             int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int nl = N >> l;
+    int64_t per = (int64_t)nl * nl;
+    int64_t p = g / per;
+    int k = (int)(g % per);
+    out[g] = pyr[p * stride + level_offset(N, l) + k];
+}
+
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+extern "C" void pt_trace_opts_default(pt_trace_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->thickness_rel = 0.0f;
+    o->eye_eps_rel = 0.0f;
+    o->max_probes_per_cell = 8;
+    o->tile_w = 8;
+    o->tile_h = 8;
+    o->start_level = -1;
+    o->flags = 0;
+}
+
+extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev,
+                                       const uint16_t *normal_oct_dev, void *stream, pt_grid **out) {
+    if (out) *out = nullptr;
+    if (!desc || !distance_dev || !normal_oct_dev || !out)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: NULL argument");
+    for (int a = 0; a < 3; ++a) {
+        if (desc->dims[a] < 2 || desc->dims[a] > 4096)
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: dims must be in [2, 4096]");
+        if (!(desc->spacing[a] > 0.0f) || !std::isfinite(desc->spacing[a]) || !std::isfinite(desc->origin[a]))
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: spacing must be finite and > 0");
+        if (!(desc->scene_max[a] > desc->scene_min[a]))
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: scene_max must exceed scene_min");
+    }
+    int N = desc->map_res, L = desc->mip_levels;
+    if (!is_pow2(N) || N < 8 || N > 4096)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: map_res must be a power of two in [8, 4096]");
+    if (L < 1 || L > kMaxLevels || (N >> (L - 1)) < 2)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: mip_levels must satisfy N >> (L-1) >= 2");
+    int64_t P = (int64_t)desc->dims[0] * desc->dims[1] * desc->dims[2];
+    if (P > (1 << 24)) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: too many probes");
+    pt_grid *g = new (std::nothrow) pt_grid();
+    if (!g) return fail(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: host allocation");
+    g->desc = *desc;
+    g->P = (int)P;
+    g->N = N;
+    g->L = L;
+    g->stride = (int64_t)level_offset(N, L);
+    hipStream_t s = (hipStream_t)stream;
+    auto cleanup = [&](pt_status st, const std::string &m) {
+        probe_grid_destroy(g);
+        return fail(st, m);
+    };
+    if (hipGetDevice(&g->device) != hipSuccess) return cleanup(PT_ERR_HIP, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g->num_cus = prop.multiProcessorCount;
+    if (hipMalloc(&g->pyr, (size_t)(P * g->stride) * sizeof(float)) != hipSuccess)
+        return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: pyramid allocation");
+    if (hipMalloc(&g->nrm, (size_t)(P * N * N) * sizeof(uint32_t)) != hipSuccess)
+        return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: normal allocation");
+    if (hipMalloc(&g->counter, 64) != hipSuccess) return cleanup(PT_ERR_OUT_OF_MEMORY, "counter allocation");
+    if (hipEventCreateWithFlags(&g->staging_free, hipEventDisableTiming) != hipSuccess)
+        return cleanup(PT_ERR_HIP, "hipEventCreate failed");
+    int64_t total = P * N * N;
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(total, 256)), dim3(256), 0, s, distance_dev, normal_oct_dev, g->pyr,
+                       g->nrm, N, g->stride, total);
+    for (int l = 1; l < L; ++l) {
+        int64_t tl = P * (int64_t)(N >> l) * (N >> l);
+        hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, N, l, g->stride, tl);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cleanup(PT_ERR_HIP, std::string("probe_grid_create launch: ") + hipGetErrorString(e));
+    *out = g;
+    return PT_OK;
+}
+
+extern "C" void probe_grid_destroy(pt_grid *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+    if (g->graph.graph) (void)hipGraphDestroy(g->graph.graph);
+    if (g->graph.views_dev) (void)hipFree(g->graph.views_dev);
+    if (g->graph.capture) (void)hipStreamDestroy(g->graph.capture);
+    if (g->pyr) (void)hipFree(g->pyr);
+    if (g->nrm) (void)hipFree(g->nrm);
+    if (g->counter) (void)hipFree(g->counter);
+    if (g->views_dev) (void)hipFree(g->views_dev);
+    if (g->views_host) (void)hipHostFree(g->views_host);
+    if (g->staging_free) (void)hipEventDestroy(g->staging_free);
+    delete g;
+}
+
+extern "C" pt_status probe_grid_read_level(const pt_grid *g, int32_t level, float *out_dev, void *stream) {
+    if (!g || !out_dev) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_read_level: NULL argument");
+    if (level < 0 || level >= g->L) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_read_level: bad level");
+    int64_t total = (int64_t)g->P * (g->N >> level) * (g->N >> level);
+    hipLaunchKernelGGL(k_read_level, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, g->pyr, out_dev,
+                       g->N, (int)level, g->stride, total);
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// trace kernels
+// ------------------------------------------------------------------------------------
+struct Outputs {
+    float *rgb;
+    float *t;
+    uint8_t *status;
+    int32_t *hit;
+};
+
+__device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult &r,
+                                             int64_t ray, const Outputs &o) {
+    float rgb[3] = {g.bg[0], g.bg[1], g.bg[2]};
+    if (r.status == ST_HIT) {
+        int idx[4];
+        float wt[4];
+        hit_radiance(g, rad, r, rgb, idx, wt);
+    }
+    o.rgb[3 * ray + 0] = rgb[0];
+    o.rgb[3 * ray + 1] = rgb[1];
+    o.rgb[3 * ray + 2] = rgb[2];
+    if (o.t) o.t[ray] = r.status == ST_HIT ? r.t : INFINITY;
+    if (o.status) o.status[ray] = (uint8_t)r.status;
+    if (o.hit) {
+        o.hit[2 * ray + 0] = r.status == ST_HIT ? r.probe : -1;
+        o.hit[2 * ray + 1] = r.status == ST_HIT ? r.texel : -1;
+    }
+}
+
+// Workgroup -> tile order that keeps neighbouring tiles on one XCD: workgroups are handed
+// to the 8 XCDs round-robin, so XCD x receives workgroups x, x+8, ...; give it one
+// contiguous run of tiles instead.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    int q = nb >> 3, rem = nb & 7;
+    int x = b & 7, slot = b >> 3;
+    return x * q + min(x, rem) + slot;
+}
+
+// One view: each wavefront owns one tw x th pixel tile.
+__global__ void __launch_bounds__(256) k_trace_view(GridDev g, ViewDev v, const uint16_t *__restrict__ rad,
+                                                    Outputs o, int tw, int th) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int nb = gridDim.x;
+    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
+    int tiles_y = (v.H + th - 1) / th;
+    if (tile >= v.tiles_x * tiles_y) return;
+    int x = (tile % v.tiles_x) * tw + lane % tw;
+    int y = (tile / v.tiles_x) * th + lane / tw;
+    if (x >= v.W || y >= v.H) return;
+    float w[3];
+    camera_ray(v, x, y, w);
+    RayResult r;
+    trace_ray(g, v.pos, w, r);
+    write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
+}
+
+__global__ void __launch_bounds__(256) k_trace_rays(GridDev g, const float *__restrict__ orig,
+                                                    const float *__restrict__ dirs, int64_t n,
+                                                    const uint16_t *__restrict__ rad, Outputs o) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float X[3] = {orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
+    float d[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+    float l2 = __fmaf_rn(d[2], d[2], __fmaf_rn(d[1], d[1], d[0] * d[0]));
+    RayResult r;
+    if (!(l2 > 0.0f) || !isfinite(l2)) {
+        r.status = ST_MISS;
+        r.probe = -1;
+        r.texel = -1;
+        r.t = INFINITY;
+    } else {
+        float inv = 1.0f / sqrtf(l2);
+        float w[3] = {d[0] * inv, d[1] * inv, d[2] * inv};
+        trace_ray(g, X, w, r);
+    }
+    write_result(g, rad, r, i, o);
+}
+
+// Persistent multi-view trace: every wavefront pops tiles from a device counter until the
+// queue is empty (every wave reaches that exit).
+__global__ void k_reset_counter(int *c) { c[0] = 0; }
+
+__global__ void __launch_bounds__(256) k_trace_persistent(GridDev g, const ViewDev *__restrict__ views, int n_views,
+                                                          int total_tiles, int *counter,
+                                                          const uint16_t *__restrict__ rad, Outputs o, int tw,
+                                                          int th) {
+    int lane = threadIdx.x & 63;
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = atomicAdd(counter, 1);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= total_tiles) return;
+        // view holding this tile (views sorted by tile_begin)
+        int lo = 0, hi = n_views - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (views[mid].tile_begin <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewDev &v = views[lo];
+        int lt = tile - v.tile_begin;
+        int x = (lt % v.tiles_x) * tw + lane % tw;
+        int y = (lt / v.tiles_x) * th + lane / tw;
+        if (x < v.W && y < v.H) {
+            float w[3];
+            camera_ray(v, x, y, w);
+            RayResult r;
+            trace_ray(g, v.pos, w, r);
+            write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
+        }
+    }
+}
+
+// Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
+__global__ void __launch_bounds__(256) k_backward_view(GridDev g, ViewDev v, const float *__restrict__ grad_rgb,
+                                                       float *__restrict__ grad_rad, int tw, int th) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int nb = gridDim.x;
+    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
+    int tiles_y = (v.H + th - 1) / th;
+    if (tile >= v.tiles_x * tiles_y) return;
+    int x = (tile % v.tiles_x) * tw + lane % tw;
+    int y = (tile / v.tiles_x) * th + lane / tw;
+    if (x >= v.W || y >= v.H) return;
+    float w[3];
+    camera_ray(v, x, y, w);
+    RayResult r;
+    trace_ray(g, v.pos, w, r);
+    if (r.status != ST_HIT) return;
+    int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
+    float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
+    float u, vv;
+    oct_encode(r.q[0], r.q[1], r.q[2], u, vv);
+    int idx[4];
+    float wt[4];
+    bilinear_taps(u, vv, g.N, idx, wt);
+    float *G = grad_rad + (int64_t)r.probe * g.N * g.N * 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (wt[k] == 0.0f) continue;
+        atomicAdd(G + 3 * idx[k] + 0, wt[k] * gr[0]);
+        atomicAdd(G + 3 * idx[k] + 1, wt[k] * gr[1]);
+        atomicAdd(G + 3 * idx[k] + 2, wt[k] * gr[2]);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// host side of the trace
+// ------------------------------------------------------------------------------------
+static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridDev &d) {
+    pt_trace_opts o;
+    if (opts) o = *opts;
+    else pt_trace_opts_default(&o);
+    memset(&d, 0, sizeof(d));
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = g->desc.dims[a];
+        d.org[a] = g->desc.origin[a];
+        d.spc[a] = g->desc.spacing[a];
+        d.smin[a] = g->desc.scene_min[a];
+        d.smax[a] = g->desc.scene_max[a];
+        d.bg[a] = o.background[a];
+    }
+    d.N = g->N;
+    d.logN = 0;
+    while ((1 << d.logN) < g->N) ++d.logN;
+    d.L = g->L;
+    d.top = (o.start_level < 0 || o.start_level > g->L - 1) ? g->L - 1 : o.start_level;
+    d.P = g->P;
+    d.stride = g->stride;
+    d.pyr = g->pyr;
+    d.nrm = g->nrm;
+    float tau = o.thickness_rel > 0.0f ? o.thickness_rel : 8.0f / (float)g->N;
+    d.tau1 = 1.0f + tau;  // +INF stays +INF: the shadow-entry test never triggers
+    float eps = o.eye_eps_rel > 0.0f ? o.eye_eps_rel : 1e-6f;
+    float ms = std::min(g->desc.spacing[0], std::min(g->desc.spacing[1], g->desc.spacing[2]));
+    d.eye_eps2 = (eps * ms) * (eps * ms);
+    d.max_probes = (o.max_probes_per_cell < 1 || o.max_probes_per_cell > 8) ? 8 : o.max_probes_per_cell;
+    return PT_OK;
+}
+
+static pt_status tile_shape(const pt_trace_opts *opts, int &tw, int &th) {
+    tw = 8;
+    th = 8;
+    if (opts && (opts->tile_w || opts->tile_h)) {
+        tw = opts->tile_w;
+        th = opts->tile_h;
+        if (tw < 1 || th < 1 || tw * th != 64)
+            return fail(PT_ERR_INVALID_ARGUMENT, "tile_w * tile_h must be 64");
+    }
+    return PT_OK;
+}
+
+static pt_status check_views(const pt_view *views, int n_views, int tw, int th, std::vector<ViewDev> &vd,
+                             int64_t &rays, int &tiles) {
+    if (!views || n_views < 1) return fail(PT_ERR_INVALID_ARGUMENT, "need at least one view");
+    vd.resize(n_views);
+    rays = 0;
+    int64_t t = 0;
+    for (int i = 0; i < n_views; ++i) {
+        const pt_view &v = views[i];
+        if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
+            return fail(PT_ERR_INVALID_ARGUMENT, "view size out of range");
+        if (!(v.tan_half_fov_y > 0.0f) || !std::isfinite(v.tan_half_fov_y))
+            return fail(PT_ERR_INVALID_ARGUMENT, "tan_half_fov_y must be finite and > 0");
+        ViewDev &d = vd[i];
+        for (int a = 0; a < 3; ++a) {
+            d.pos[a] = v.pos[a];
+            d.right[a] = v.right[a];
+            d.up[a] = v.up[a];
+            d.fwd[a] = v.fwd[a];
+        }
+        d.tanh = v.tan_half_fov_y;
+        d.W = v.width;
+        d.H = v.height;
+        d.ray_offset = rays;
+        d.tiles_x = (v.width + tw - 1) / tw;
+        d.tile_begin = (int)t;
+        t += (int64_t)d.tiles_x * ((v.height + th - 1) / th);
+        rays += (int64_t)v.width * v.height;
+    }
+    if (t > (int64_t)1 << 30) return fail(PT_ERR_INVALID_ARGUMENT, "too many tiles");
+    tiles = (int)t;
+    return PT_OK;
+}
+
+static pt_status upload_views(pt_grid *g, const std::vector<ViewDev> &vd, hipStream_t s) {
+    int n = (int)vd.size();
+    if (n > g->views_cap) {
+        HIP_TRY(hipEventSynchronize(g->staging_free));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (g->views_dev) HIP_TRY(hipFree(g->views_dev));
+        if (g->views_host) HIP_TRY(hipHostFree(g->views_host));
+        g->views_dev = nullptr;
+        g->views_host = nullptr;
+        int cap = std::max(64, n);
+        if (hipMalloc(&g->views_dev, sizeof(ViewDev) * cap) != hipSuccess)
+            return fail(PT_ERR_OUT_OF_MEMORY, "view table allocation");
+        if (hipHostMalloc(&g->views_host, sizeof(ViewDev) * cap, hipHostMallocDefault) != hipSuccess)
+            return fail(PT_ERR_OUT_OF_MEMORY, "view staging allocation");
+        g->views_cap = cap;
+    }
+    // the staging buffer may still feed the previous copy
+    HIP_TRY(hipEventSynchronize(g->staging_free));
+    memcpy(g->views_host, vd.data(), sizeof(ViewDev) * n);
+    HIP_TRY(hipMemcpyAsync(g->views_dev, g->views_host, sizeof(ViewDev) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(g->staging_free, s));
+    return PT_OK;
+}
+
+static unsigned persistent_blocks(const pt_grid *g) { return (unsigned)(g->num_cus * 8); }
+
+static pt_status launch_persistent(pt_grid *g, const GridDev &d, const ViewDev *views_dev, int n_views, int tiles,
+                                   const uint16_t *rad, const Outputs &o, int tw, int th, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g->counter);
+    hipLaunchKernelGGL(k_trace_persistent, dim3(persistent_blocks(g)), dim3(256), 0, s, d, views_dev, n_views, tiles,
+                       g->counter, rad, o, tw, th);
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+static void append_bytes(std::vector<unsigned char> &k, const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    k.insert(k.end(), c, c + n);
+}
+
+static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewDev> &vd, int tiles,
+                           const uint16_t *rad, const Outputs &o, int tw, int th, hipStream_t s) {
+    std::vector<unsigned char> key;
+    append_bytes(key, &d, sizeof(d));
+    append_bytes(key, vd.data(), vd.size() * sizeof(ViewDev));
+    append_bytes(key, &rad, sizeof(rad));
+    append_bytes(key, &o, sizeof(o));
+    append_bytes(key, &tw, sizeof(tw));
+    append_bytes(key, &th, sizeof(th));
+    GraphCache &gc = g->graph;
+    if (!gc.exec || gc.key != key) {
+        if (gc.exec) {
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipGraphExecDestroy(gc.exec));
+            gc.exec = nullptr;
+        }
+        if (gc.graph) {
+            HIP_TRY(hipGraphDestroy(gc.graph));
+            gc.graph = nullptr;
+        }
+        int n = (int)vd.size();
+        if (n > gc.cap) {
+            HIP_TRY(hipStreamSynchronize(s));
+            if (gc.views_dev) HIP_TRY(hipFree(gc.views_dev));
+            gc.views_dev = nullptr;
+            if (hipMalloc(&gc.views_dev, sizeof(ViewDev) * n) != hipSuccess)
+                return fail(PT_ERR_OUT_OF_MEMORY, "graph view table allocation");
+            gc.cap = n;
+        }
+        // the table is baked into this graph: copy it now, outside the capture
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(gc.views_dev, vd.data(), sizeof(ViewDev) * n, hipMemcpyHostToDevice));
+        // capture on a private non-blocking stream (the caller's may be the legacy default
+        // stream, which cannot capture); the graph is then launched on the caller's stream
+        if (!gc.capture) HIP_TRY(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal));
+        pt_status st = launch_persistent(g, d, gc.views_dev, n, tiles, rad, o, tw, th, gc.capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(gc.capture, &graph);
+        if (st != PT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(PT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        gc.graph = graph;
+        HIP_TRY(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+        gc.key = key;
+    }
+    HIP_TRY(hipGraphLaunch(gc.exec, s));
+    return PT_OK;
+}
+
+static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_view *views, int n_views,
+                            const Outputs &o, const pt_trace_opts *opts, hipStream_t s) {
+    pt_grid *g = const_cast<pt_grid *>(cg);
+    int tw, th;
+    pt_status st = tile_shape(opts, tw, th);
+    if (st != PT_OK) return st;
+    std::vector<ViewDev> vd;
+    int64_t rays;
+    int tiles;
+    st = check_views(views, n_views, tw, th, vd, rays, tiles);
+    if (st != PT_OK) return st;
+    GridDev d;
+    make_griddev(g, opts, d);
+    uint32_t flags = opts ? opts->flags : 0;
+    if (flags & PT_FLAG_GRAPH) return run_graph(g, d, vd, tiles, rad, o, tw, th, s);
+    if (flags & PT_FLAG_PERSISTENT) {
+        st = upload_views(g, vd, s);
+        if (st != PT_OK) return st;
+        return launch_persistent(g, d, g->views_dev, n_views, tiles, rad, o, tw, th, s);
+    }
+    for (int i = 0; i < n_views; ++i) {
+        int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
+        unsigned nb = (unsigned)((vt + 3) / 4);
+        hipLaunchKernelGGL(k_trace_view, dim3(nb), dim3(256), 0, s, d, vd[i], rad, o, tw, th);
+    }
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status probe_trace(const pt_grid *g, const uint16_t *radiance_dev, const pt_view *views_host,
+                                 int32_t n_views, float *rgb_dev, float *t_dev, uint8_t *status_dev, int32_t *hit_dev,
+                                 const pt_trace_opts *opts, void *stream) {
+    if (!g || !radiance_dev || !rgb_dev) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace: NULL argument");
+    Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
+    return trace_impl(g, radiance_dev, views_host, n_views, o, opts, (hipStream_t)stream);
+}
+
+extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance_dev, const float *origins_dev,
+                                      const float *dirs_dev, int64_t n, float *rgb_dev, float *t_dev,
+                                      uint8_t *status_dev, int32_t *hit_dev, const pt_trace_opts *opts,
+                                      void *stream) {
+    if (!g || !radiance_dev || !origins_dev || !dirs_dev || !rgb_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: NULL argument");
+    if (n < 0) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: n < 0");
+    if (n == 0) return PT_OK;
+    GridDev d;
+    make_griddev(g, opts, d);
+    Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
+    hipLaunchKernelGGL(k_trace_rays, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, d, origins_dev,
+                       dirs_dev, n, radiance_dev, o);
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views_host, int32_t n_views,
+                                          const float *grad_rgb_dev, float *grad_radiance_dev,
+                                          const pt_trace_opts *opts, void *stream) {
+    if (!g || !grad_rgb_dev || !grad_radiance_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
+    int tw, th;
+    pt_status st = tile_shape(opts, tw, th);
+    if (st != PT_OK) return st;
+    std::vector<ViewDev> vd;
+    int64_t rays;
+    int tiles;
+    st = check_views(views_host, n_views, tw, th, vd, rays, tiles);
+    if (st != PT_OK) return st;
+    GridDev d;
+    make_griddev(g, opts, d);
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n_views; ++i) {
+        int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
+        unsigned nb = (unsigned)((vt + 3) / 4);
+        hipLaunchKernelGGL(k_backward_view, dim3(nb), dim3(256), 0, s, d, vd[i], grad_rgb_dev, grad_radiance_dev, tw,
+                           th);
+    }
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_dev, const pt_view *views_host,
+                                    int32_t n_views, float *rgb_dev, pt_trace_opts *opts, void *stream) {
+    if (!g || !radiance_dev || !views_host || !rgb_dev || !opts)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_autotune: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    static const int shapes[][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = INFINITY;
+    pt_trace_opts bo = *opts;
+    Outputs o{rgb_dev, nullptr, nullptr, nullptr};
+    for (auto &sh : shapes) {
+        for (int lv = g->L - 1; lv >= std::max(0, g->L - 3); --lv) {
+            pt_trace_opts c = *opts;
+            c.tile_w = sh[0];
+            c.tile_h = sh[1];
+            c.start_level = lv;
+            pt_status st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);  // warm-up
+            if (st != PT_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            HIP_TRY(hipEventRecord(e0, s));
+            for (int r = 0; r < 3; ++r) trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bo = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    opts->tile_w = bo.tile_w;
+    opts->tile_h = bo.tile_h;
+    opts->start_level = bo.start_level;
+    return PT_OK;
+}

@@ -1,0 +1,533 @@
+// Device-side probe-grid tracing for gfx950 (wave64).  One camera ray per lane.
+//
+// Method: arXiv 2507.14624 (Overview; Methodology > Ray Tracing Using One Probe, Ray
+// Trace Using Multiple Probes; appendix traceOneProbe, traceOneRaySegment,
+// lowResolutionTracing, highResolutionTracing).  See include/probetrace.h for the
+// contract.  All arithmetic is FP32; the file is compiled with -ffp-contract=off so
+// every fused multiply-add below is explicit and a quantity computed twice from the
+// same operands is bitwise identical (the march relies on that: a coarse texel
+// boundary and the fine boundary on the same plane must produce the same t, and an
+// octant cut on a cell's own plane must equal the cell boundary exactly).
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pt {
+
+enum { ST_MISS = 0, ST_HIT = 1, ST_UNKNOWN = 2 };
+
+constexpr int kMaxLevels = 13;
+
+// Everything a trace kernel needs about the grid, passed by value.
+struct GridDev {
+    int n[3];        // probes per axis
+    float org[3];    // probe (0,0,0)
+    float spc[3];    // spacing
+    float smin[3], smax[3];
+    int N;           // level-0 map resolution (power of two)
+    int logN;
+    int L;           // pyramid levels
+    int top;         // level the march starts at
+    int P;           // number of probes
+    int64_t stride;  // floats per probe pyramid block
+    const float *__restrict__ pyr;     // [P][stride]: level 0, then 1, ... (row-major per level)
+    const uint32_t *__restrict__ nrm;  // [P][N*N] packed FP16 (u, v) of the stored normal
+    float eye_eps2;  // (eye_eps_rel * min spacing)^2
+    float tau1;      // 1 + thickness
+    float bg[3];
+    int max_probes;
+};
+
+// Offset of level l inside a probe block: sum_{m<l} (N>>m)^2 = 4 (N^2 - (N>>l)^2) / 3.
+__host__ __device__ __forceinline__ int level_offset(int N, int l) {
+    int nl = N >> l;
+    return (4 * (N * N - nl * nl)) / 3;
+}
+
+// grid plane / probe coordinate along axis a (shared by the cell iterator and the probes)
+__device__ __forceinline__ float grid_coord(const GridDev &g, int a, int idx) {
+    return __fmaf_rn((float)idx, g.spc[a], g.org[a]);
+}
+
+// ray parameter where coordinate a reaches `plane` (shared by cell walls and octant cuts)
+__device__ __forceinline__ float plane_t(float plane, float x, float w) { return (plane - x) / w; }
+
+__device__ __forceinline__ float sgnp(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
+
+__device__ __forceinline__ float half_bits(uint16_t b) { return __half2float(__ushort_as_half(b)); }
+
+// Octahedral encode (z fold axis), returns (u, v) in [-1, 1]^2.
+__device__ __forceinline__ void oct_encode(float x, float y, float z, float &u, float &v) {
+    float inv = 1.0f / (fabsf(x) + fabsf(y) + fabsf(z));
+    float px = x * inv, py = y * inv, pz = z * inv;
+    if (pz >= 0.0f) {
+        u = px;
+        v = py;
+    } else {
+        u = (1.0f - fabsf(py)) * sgnp(px);
+        v = (1.0f - fabsf(px)) * sgnp(py);
+    }
+}
+
+// Octahedral decode, not normalised (only the sign of n . w is used).
+__device__ __forceinline__ void oct_decode_unnorm(float u, float v, float &x, float &y, float &z) {
+    z = 1.0f - fabsf(u) - fabsf(v);
+    if (z < 0.0f) {
+        x = (1.0f - fabsf(v)) * sgnp(u);
+        y = (1.0f - fabsf(u)) * sgnp(v);
+    } else {
+        x = u;
+        y = v;
+    }
+}
+
+// Bilinear taps at (u, v) with the octahedral border wrap: beyond an edge of the square
+// the map continues mirrored along that edge.
+__device__ __forceinline__ void bilinear_taps(float u, float v, int N, int idx[4], float wt[4]) {
+    float x = __fmaf_rn(u + 1.0f, 0.5f * (float)N, -0.5f);
+    float y = __fmaf_rn(v + 1.0f, 0.5f * (float)N, -0.5f);
+    float fi = floorf(x), fj = floorf(y);
+    float fx = x - fi, fy = y - fj;
+    int i0 = (int)fi, j0 = (int)fj;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int i = i0 + (k & 1), j = j0 + (k >> 1);
+        if (i < 0) {
+            i = 0;
+            j = N - 1 - j;
+        } else if (i >= N) {
+            i = N - 1;
+            j = N - 1 - j;
+        }
+        if (j < 0) {
+            j = 0;
+            i = N - 1 - i;
+        } else if (j >= N) {
+            j = N - 1;
+            i = N - 1 - i;
+        }
+        i = min(max(i, 0), N - 1);
+        j = min(max(j, 0), N - 1);
+        idx[k] = j * N + i;
+        wt[k] = ((k & 1) ? fx : 1.0f - fx) * ((k >> 1) ? fy : 1.0f - fy);
+    }
+}
+
+__device__ __forceinline__ float rho2_at(const float Xp[3], const float w[3], float t) {
+    float a = __fmaf_rn(t, w[0], Xp[0]);
+    float b = __fmaf_rn(t, w[1], Xp[1]);
+    float c = __fmaf_rn(t, w[2], Xp[2]);
+    return __fmaf_rn(c, c, __fmaf_rn(b, b, a * a));
+}
+
+// One straight piece of the projected ray: x = A/L, y = B/L in texel units, with A, B, L
+// linear in the ray point.  A texel boundary x = c is the plane A - c L = 0 through the
+// probe; the ray reaches it at t = (c L0 - A0) / (A1 - c L1), and only if A1 - c L1 has
+// the sign of the motion along x.
+struct Piece {
+    float A0, A1, B0, B1, L0, L1;
+    float ts, te;
+    int dx, dy;
+    int ilo, ihi, jlo, jhi;  // quadrant of the octant (level 0)
+};
+
+__device__ __forceinline__ float cross_t(int c, int dir, float P0, float P1, float L0, float L1) {
+    float fc = (float)c;
+    float den = __fmaf_rn(-fc, L1, P1);
+    float num = __fmaf_rn(fc, L0, -P0);
+    return ((float)dir * den > 0.0f) ? num / den : INFINITY;
+}
+
+__device__ __forceinline__ float next_x(const Piece &s, int I, int l) {
+    if (s.dx == 0) return INFINITY;
+    int c = (s.dx > 0 ? I + 1 : I) << l;
+    if (c <= s.ilo || c > s.ihi) return INFINITY;
+    return cross_t(c, s.dx, s.A0, s.A1, s.L0, s.L1);
+}
+__device__ __forceinline__ float next_y(const Piece &s, int J, int l) {
+    if (s.dy == 0) return INFINITY;
+    int c = (s.dy > 0 ? J + 1 : J) << l;
+    if (c <= s.jlo || c > s.jhi) return INFINITY;
+    return cross_t(c, s.dy, s.B0, s.B1, s.L0, s.L1);
+}
+
+__device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const float w[3], float ts, float te,
+                                            int N) {
+    float tm = 0.5f * (ts + te);
+    float sx = sgnp(__fmaf_rn(tm, w[0], Xp[0]));
+    float sy = sgnp(__fmaf_rn(tm, w[1], Xp[1]));
+    float sz = sgnp(__fmaf_rn(tm, w[2], Xp[2]));
+    float hN = 0.5f * (float)N;
+    // L = sx x + sy y + sz z; u = (x + [z<0] sx|z|)/L, v = (y + [z<0] sy|z|)/L; A = (U+L) N/2
+    float uz = sz < 0.0f ? -sx : 0.0f, vz = sz < 0.0f ? -sy : 0.0f;
+    float a0 = hN * (1.0f + sx), a1 = hN * sy, a2 = hN * (uz + sz);
+    float b0 = hN * sx, b1 = hN * (1.0f + sy), b2 = hN * (vz + sz);
+    s.A0 = __fmaf_rn(a2, Xp[2], __fmaf_rn(a1, Xp[1], a0 * Xp[0]));
+    s.A1 = __fmaf_rn(a2, w[2], __fmaf_rn(a1, w[1], a0 * w[0]));
+    s.B0 = __fmaf_rn(b2, Xp[2], __fmaf_rn(b1, Xp[1], b0 * Xp[0]));
+    s.B1 = __fmaf_rn(b2, w[2], __fmaf_rn(b1, w[1], b0 * w[0]));
+    s.L0 = __fmaf_rn(sz, Xp[2], __fmaf_rn(sy, Xp[1], sx * Xp[0]));
+    s.L1 = __fmaf_rn(sz, w[2], __fmaf_rn(sy, w[1], sx * w[0]));
+    float gx = __fmaf_rn(s.A1, s.L0, -(s.A0 * s.L1));
+    float gy = __fmaf_rn(s.B1, s.L0, -(s.B0 * s.L1));
+    s.dx = gx > 0.0f ? 1 : (gx < 0.0f ? -1 : 0);
+    s.dy = gy > 0.0f ? 1 : (gy < 0.0f ? -1 : 0);
+    s.ts = ts;
+    s.te = te;
+    s.ilo = sx > 0.0f ? N / 2 : 0;
+    s.ihi = sx > 0.0f ? N - 1 : N / 2 - 1;
+    s.jlo = sy > 0.0f ? N / 2 : 0;
+    s.jhi = sy > 0.0f ? N - 1 : N / 2 - 1;
+}
+
+// Texel-unit coordinates of the ray point at t, evaluated from the point itself.
+__device__ __forceinline__ void piece_xy(const Piece &s, const float Xp[3], const float w[3], float t, int N,
+                                         float &x, float &y, float &L) {
+    // the linear forms are re-derived from A/B/L at the origin and along w
+    L = __fmaf_rn(t, s.L1, s.L0);
+    float A = __fmaf_rn(t, s.A1, s.A0);
+    float B = __fmaf_rn(t, s.B1, s.B0);
+    x = A / L;
+    y = B / L;
+}
+
+struct Fire {
+    int i, j;       // level-0 texel
+    float tin;      // entry parameter
+    float rin2;     // rho^2 at entry
+};
+
+// Hierarchical march of one piece over the probe's MIN pyramid (block = the probe's
+// pyramid).  Returns true at the first level-0 texel with stored r < max rho.
+__device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, const float Xp[3], const float w[3],
+                            const Piece &s, Fire &f) {
+    const int N = g.N;
+    float xs, ys, Ls;
+    piece_xy(s, Xp, w, s.ts, N, xs, ys, Ls);
+    if (!(Ls > 0.0f)) {  // the piece starts at the probe origin itself
+        piece_xy(s, Xp, w, 0.5f * (s.ts + s.te), N, xs, ys, Ls);
+        if (!(Ls > 0.0f)) {
+            xs = (float)s.ilo;
+            ys = (float)s.jlo;
+        }
+    }
+    int i0 = min(max((int)floorf(xs), s.ilo), s.ihi);
+    int j0 = min(max((int)floorf(ys), s.jlo), s.jhi);
+    int l = g.top;
+    int I = i0 >> l, J = j0 >> l;
+    int off = level_offset(N, l);
+    float t = s.ts;
+    float rc2 = rho2_at(Xp, w, t);
+    float tx = next_x(s, I, l), ty = next_y(s, J, l);
+    const int guard = 24 * N + 64;
+    for (int it = 0; it < guard; ++it) {
+        float tmin = fminf(tx, ty);
+        float texit = fmaxf(fminf(tmin, s.te), t);
+        float re2 = rho2_at(Xp, w, texit);
+        float m2 = fmaxf(rc2, re2);
+        int nl = N >> l;
+        float M = blk[off + J * nl + I];
+        // coarse levels test conservatively (the min over a parent must not miss a child
+        // whose ray span's rho^2 rounds a little above the parent's endpoints)
+        float lim = l == 0 ? m2 : m2 * 1.0000153f;
+        bool fire = (M < 0.0f) || (M * M < lim);
+        if (fire) {
+            if (l == 0) {
+                f.i = I;
+                f.j = J;
+                f.tin = t;
+                f.rin2 = rc2;
+                return true;
+            }
+            // descend into the child that holds the ray point at t
+            float x, y, Lt;
+            piece_xy(s, Xp, w, t, N, x, y, Lt);
+            --l;
+            float sc = 1.0f / (float)(1 << l);
+            int ci = (int)floorf(x * sc), cj = (int)floorf(y * sc);
+            ci = min(max(ci, 2 * I), 2 * I + 1);
+            cj = min(max(cj, 2 * J), 2 * J + 1);
+            I = min(max(ci, s.ilo >> l), s.ihi >> l);
+            J = min(max(cj, s.jlo >> l), s.jhi >> l);
+            off = level_offset(N, l);
+            tx = next_x(s, I, l);
+            ty = next_y(s, J, l);
+            continue;
+        }
+        if (!(tmin < s.te)) return false;  // the piece ends inside this texel
+        bool stepx = tx == tmin, stepy = ty == tmin;
+        int Io = I, Jo = J;
+        t = texit;
+        rc2 = re2;
+        if (stepx) I = min(max(I + s.dx, s.ilo >> l), s.ihi >> l);
+        if (stepy) J = min(max(J + s.dy, s.jlo >> l), s.jhi >> l);
+        bool up = false;
+        while (l < g.top && (((I >> 1) != (Io >> 1)) || ((J >> 1) != (Jo >> 1)))) {
+            I >>= 1;
+            J >>= 1;
+            Io >>= 1;
+            Jo >>= 1;
+            ++l;
+            up = true;
+        }
+        if (up) {
+            off = level_offset(N, l);
+            tx = next_x(s, I, l);
+            ty = next_y(s, J, l);
+        } else {
+            if (stepx) tx = next_x(s, I, l);
+            if (stepy) ty = next_y(s, J, l);
+        }
+    }
+    return false;
+}
+
+struct ProbeResult {
+    int status;
+    int texel;     // j*N + i
+    float t;       // hit distance
+    float q[3];    // hit point relative to the probe
+};
+
+// traceOneProbe over [ta, tb] for probe (pi, pj, pk).
+__device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const float X[3], const float w[3], float ta,
+                            float tb, ProbeResult &res) {
+    const int N = g.N;
+    const int p = pi + g.n[0] * (pj + g.n[1] * pk);
+    float O[3] = {grid_coord(g, 0, pi), grid_coord(g, 1, pj), grid_coord(g, 2, pk)};
+    float Xp[3] = {X[0] - O[0], X[1] - O[1], X[2] - O[2]};
+    res.status = ST_MISS;
+    res.texel = -1;
+    const float *blk = g.pyr + (int64_t)p * g.stride;
+    float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
+    if (d2 <= g.eye_eps2) {
+        // eye aligned with the probe: every ray point maps to oct(w)
+        float u, v;
+        oct_encode(w[0], w[1], w[2], u, v);
+        int i = min(max((int)floorf(__fmaf_rn(u + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
+        int j = min(max((int)floorf(__fmaf_rn(v + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
+        float r = blk[j * N + i];
+        if (r >= ta && r <= tb) {
+            res.status = ST_HIT;
+            res.texel = j * N + i;
+            res.t = r;
+            res.q[0] = w[0];
+            res.q[1] = w[1];
+            res.q[2] = w[2];
+        }
+        return;
+    }
+    // split [ta, tb] where a coordinate of X - O + t w changes sign (at most 3 cuts)
+    float c0 = INFINITY, c1 = INFINITY, c2 = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (w[a] != 0.0f) {
+            float tz = plane_t(O[a], X[a], w[a]);
+            if (tz > ta && tz < tb) {
+                // insert into the sorted triple
+                if (tz < c0) {
+                    c2 = c1;
+                    c1 = c0;
+                    c0 = tz;
+                } else if (tz < c1) {
+                    c2 = c1;
+                    c1 = tz;
+                } else {
+                    c2 = tz;
+                }
+            }
+        }
+    }
+    int nc = (c0 < INFINITY) + (c1 < INFINITY) + (c2 < INFINITY);
+    float lo = ta;
+    for (int sgi = 0; sgi <= nc; ++sgi) {
+        float hi = sgi == nc ? tb : (sgi == 0 ? c0 : (sgi == 1 ? c1 : c2));
+        Piece s;
+        piece_setup(s, Xp, w, lo, hi, N);
+        Fire f;
+        if (march_piece(g, blk, Xp, w, s, f)) {
+            int k = f.j * N + f.i;
+            float r = blk[k];
+            res.texel = k;
+            float thr = r * g.tau1;
+            // shadow entry: the ray entered the texel behind the stored surface
+            bool shadow = (thr < 0.0f) || (f.rin2 > thr * thr);
+            if (shadow) {
+                res.status = ST_UNKNOWN;
+                return;
+            }
+            uint32_t nb = g.nrm[(int64_t)p * N * N + k];
+            float nx, ny, nz;
+            oct_decode_unnorm(half_bits((uint16_t)(nb & 0xffffu)), half_bits((uint16_t)(nb >> 16)), nx, ny, nz);
+            float nd = __fmaf_rn(nz, w[2], __fmaf_rn(ny, w[1], nx * w[0]));
+            if (!(nd < 0.0f)) {
+                res.status = ST_UNKNOWN;
+                return;
+            }
+            res.status = ST_HIT;
+            float th;
+            if (f.rin2 >= r * r) {
+                th = f.tin;
+            } else {
+                // larger root of |Xp + t w| = r, cancellation-free
+                float b = __fmaf_rn(Xp[2], w[2], __fmaf_rn(Xp[1], w[1], Xp[0] * w[0]));
+                float px = __fmaf_rn(-b, w[0], Xp[0]);
+                float py = __fmaf_rn(-b, w[1], Xp[1]);
+                float pz = __fmaf_rn(-b, w[2], Xp[2]);
+                float dp = sqrtf(__fmaf_rn(pz, pz, __fmaf_rn(py, py, px * px)));
+                float disc = fmaxf((r - dp) * (r + dp), 0.0f);
+                float sq = sqrtf(disc);
+                float dist = sqrtf(d2);
+                th = b <= 0.0f ? sq - b : ((r - dist) * (r + dist)) / (b + sq);
+            }
+            res.t = th;
+            res.q[0] = __fmaf_rn(th, w[0], Xp[0]);
+            res.q[1] = __fmaf_rn(th, w[1], Xp[1]);
+            res.q[2] = __fmaf_rn(th, w[2], Xp[2]);
+            return;
+        }
+        lo = hi;
+    }
+}
+
+struct RayResult {
+    int status;
+    int probe;
+    int texel;
+    float t;
+    float q[3];  // hit point relative to the hit probe
+};
+
+// One camera ray (X, w unit): grid iterator over cells, 8 cage probes closest to the eye
+// first, fall-through on MISS and UNKNOWN.
+__device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], RayResult &out) {
+    out.status = ST_MISS;
+    out.probe = -1;
+    out.texel = -1;
+    out.t = INFINITY;
+    // until the ray leaves the scene box (slightly enlarged)
+    float tfar = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float t = INFINITY;
+        if (w[a] > 0.0f) t = plane_t(g.smax[a], X[a], w[a]);
+        else if (w[a] < 0.0f) t = plane_t(g.smin[a], X[a], w[a]);
+        tfar = fminf(tfar, t);
+    }
+    tfar = tfar * 1.0001f;
+    if (!(tfar > 0.0f)) return;
+    int cell[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float q = (X[a] - g.org[a]) / g.spc[a];
+        cell[a] = min(max((int)floorf(q), 0), g.n[a] - 2);
+    }
+    bool any_unknown = false;
+    float ta = 0.0f;
+    const int max_cells = g.n[0] + g.n[1] + g.n[2];
+    for (int ci = 0; ci < max_cells; ++ci) {
+        float tn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int pidx = -1;
+            if (w[a] > 0.0f && cell[a] + 1 <= g.n[a] - 2) pidx = cell[a] + 1;
+            else if (w[a] < 0.0f && cell[a] >= 1) pidx = cell[a];
+            tn[a] = pidx >= 0 ? plane_t(grid_coord(g, a, pidx), X[a], w[a]) : INFINITY;
+        }
+        float tb = fminf(fminf(fminf(tn[0], tn[1]), tn[2]), tfar);
+        // cage order: squared distance to the eye, ties by corner code
+        float key[8];
+        int code[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float dx = grid_coord(g, 0, cell[0] + (c & 1)) - X[0];
+            float dy = grid_coord(g, 1, cell[1] + ((c >> 1) & 1)) - X[1];
+            float dz = grid_coord(g, 2, cell[2] + (c >> 2)) - X[2];
+            key[c] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            code[c] = c;
+        }
+        // insertion sort, fully unrolled (stable: equal keys keep corner-code order)
+#pragma unroll
+        for (int a = 1; a < 8; ++a) {
+#pragma unroll
+            for (int b = a; b > 0; --b) {
+                bool sw = key[b] < key[b - 1];
+                float k0 = key[b - 1], k1 = key[b];
+                int c0 = code[b - 1], c1 = code[b];
+                key[b - 1] = sw ? k1 : k0;
+                key[b] = sw ? k0 : k1;
+                code[b - 1] = sw ? c1 : c0;
+                code[b] = sw ? c0 : c1;
+            }
+        }
+        for (int rk = 0; rk < g.max_probes; ++rk) {
+            int c = code[0];
+            // rotate the next code into slot 0 without dynamic register indexing
+#pragma unroll
+            for (int m = 0; m < 7; ++m) code[m] = code[m + 1];
+            ProbeResult pr;
+            trace_probe(g, cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2), X, w, ta, tb, pr);
+            if (pr.status == ST_HIT) {
+                out.status = ST_HIT;
+                out.probe = (cell[0] + (c & 1)) + g.n[0] * ((cell[1] + ((c >> 1) & 1)) + g.n[1] * (cell[2] + (c >> 2)));
+                out.texel = pr.texel;
+                out.t = pr.t;
+                out.q[0] = pr.q[0];
+                out.q[1] = pr.q[1];
+                out.q[2] = pr.q[2];
+                return;
+            }
+            if (pr.status == ST_UNKNOWN) any_unknown = true;
+        }
+        if (!(tb < tfar)) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (tn[a] == tb) cell[a] += w[a] > 0.0f ? 1 : -1;
+        ta = tb;
+    }
+    out.status = any_unknown ? ST_UNKNOWN : ST_MISS;
+}
+
+// Pinhole ray of pixel (x, y).
+struct ViewDev {
+    float pos[3], right[3], up[3], fwd[3];
+    float tanh;
+    int W, H;
+    int64_t ray_offset;  // first ray of this view in the output arrays
+    int tiles_x;         // tiles per row
+    int tile_begin;      // first tile index of this view in a multi-view launch
+};
+
+__device__ __forceinline__ void camera_ray(const ViewDev &v, int x, int y, float w[3]) {
+    float fw = (float)v.W, fh = (float)v.H;
+    float a = (((float)(2 * x + 1)) / fw - 1.0f) * (fw / fh) * v.tanh;
+    float b = (1.0f - ((float)(2 * y + 1)) / fh) * v.tanh;
+    float d0 = __fmaf_rn(b, v.up[0], __fmaf_rn(a, v.right[0], v.fwd[0]));
+    float d1 = __fmaf_rn(b, v.up[1], __fmaf_rn(a, v.right[1], v.fwd[1]));
+    float d2 = __fmaf_rn(b, v.up[2], __fmaf_rn(a, v.right[2], v.fwd[2]));
+    float inv = 1.0f / sqrtf(__fmaf_rn(d2, d2, __fmaf_rn(d1, d1, d0 * d0)));
+    w[0] = d0 * inv;
+    w[1] = d1 * inv;
+    w[2] = d2 * inv;
+}
+
+// Radiance of a HIT: bilinear fetch of the hit probe's map in the direction of the hit
+// point; also returns the taps for the adjoint.
+__device__ __forceinline__ void hit_radiance(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult &r,
+                                             float rgb[3], int idx[4], float wt[4]) {
+    float u, v;
+    oct_encode(r.q[0], r.q[1], r.q[2], u, v);
+    bilinear_taps(u, v, g.N, idx, wt);
+    const uint16_t *R = rad + (int64_t)r.probe * g.N * g.N * 3;
+    rgb[0] = rgb[1] = rgb[2] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint16_t *px = R + 3 * idx[k];
+        rgb[0] = __fmaf_rn(wt[k], half_bits(px[0]), rgb[0]);
+        rgb[1] = __fmaf_rn(wt[k], half_bits(px[1]), rgb[1]);
+        rgb[2] = __fmaf_rn(wt[k], half_bits(px[2]), rgb[2]);
+    }
+}
+
+}  // namespace pt

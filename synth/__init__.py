@@ -115,12 +115,6 @@ class View:
         return (self.pos, self.right, self.up, self.fwd, self.tan_half_fov_y, self.width, self.height)
 
 
-def _box_point_dist(p, c, h):
-    q = np.abs(p - c) - h
-    outside = np.linalg.norm(np.maximum(q, 0.0))
-    return outside if outside > 0 else float(np.max(q))
-
-
 def make_scene(seed: int, dims, spacing: float, k_range) -> Scene:
     """Draw a seeded room of boxes and spheres (module docstring recipe)."""
     rng = PCG32(seed)
@@ -130,8 +124,8 @@ def make_scene(seed: int, dims, spacing: float, k_range) -> Scene:
     room_max = np.array(dims, dtype=np.float64) * s
     walls = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(6)])
     nx, ny, nz = dims
-    probes = [np.array([origin + i * s, origin + j * s, origin + k * s])
-              for k in range(nz) for j in range(ny) for i in range(nx)]
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    probes = origin + s * np.stack([ii, jj, kk], -1).reshape(-1, 3).astype(np.float64)
     K = rng.randint(k_range[0], k_range[1])
     types, params, albs = [], [], []
     for _ in range(K):
@@ -143,11 +137,14 @@ def make_scene(seed: int, dims, spacing: float, k_range) -> Scene:
                 thin = rng.randint(0, 2)
                 h[2] = rng.uniform(0.05, 0.35) * s
                 h[[2, thin]] = h[[thin, 2]]
-                ok = all(_box_point_dist(p, c, h) >= 0.05 * s for p in probes)
+                q = np.abs(probes - c) - h
+                outside = np.linalg.norm(np.maximum(q, 0.0), axis=1)
+                dist = np.where(outside > 0, outside, q.max(axis=1))
+                ok = bool(np.all(dist >= 0.05 * s))
                 par = np.concatenate([c, h])
             else:
                 r = rng.uniform(0.1, 0.4) * s
-                ok = all(np.linalg.norm(p - c) - r >= 0.05 * s for p in probes)
+                ok = bool(np.all(np.linalg.norm(probes - c, axis=1) - r >= 0.05 * s))
                 par = np.concatenate([c, [r, 0.0, 0.0]])
             alb = [rng.uniform(0.1, 0.9) for _ in range(3)]
             if ok:

@@ -1,0 +1,158 @@
+"""Radiance adjoint on the GPU (probe_trace_backward, ProbeTraceFn) against the oracle.
+
+Tolerance per texel-channel:  |g_gpu - g_oracle| <= 1e-5 sum|w g| + 1e-3 sum|g| + 1e-8,
+where the sums run over the (ray, tap) pairs that touch that texel: the first term is
+FP32 atomic accumulation order, the second the single-precision bilinear weights (the
+same 1e-3 the forward allows on rgb).  Rays on which GPU and oracle disagree (all inside
+the float margin, checked by the forward parity tests) are given zero gradient on both
+sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from conftest import workload
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _pt():
+    import paper_2507_14624_amd as pt
+    pt.load_library()
+    return pt
+
+
+def _setup(name, **kw):
+    pt = _pt()
+    scene, probes, views = workload(name, **kw)
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    return pt, scene, probes, views, grid, rad
+
+
+def _check_grad(pt, probes, grid, rad, views, seed=0):
+    og = oracle.Grid.from_probes(probes)
+    res = pt.probe_trace(grid, rad, views)
+    res = {k: v.cpu().numpy() for k, v in res.items()}
+    o_parts, d_parts = [], []
+    for v in views:
+        o, d = oracle.view_rays(*v.as_tuple())
+        o_parts.append(o)
+        d_parts.append(d)
+    orc = oracle.trace(og, np.concatenate(o_parts), np.concatenate(d_parts))
+    s = compare(res, orc)
+    rng = np.random.default_rng(seed)
+    g = rng.normal(size=(s["n"], 3)).astype(np.float32)
+    g[s["disagree_idx"]] = 0.0
+    gg = torch.zeros((probes.n_probes, probes.N, probes.N, 3), dtype=torch.float32, device="cuda")
+    pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gg)
+    got = gg.cpu().numpy().astype(np.float64)
+    ref = oracle.vjp(og, orc, g.astype(np.float64))
+    wabs = oracle.vjp(og, orc, np.abs(g).astype(np.float64))
+    # sum |g| over the (ray, tap) pairs per texel: vjp with unit weights
+    unit = dict(orc)
+    unit["wts"] = (orc["wts"] != 0).astype(np.float64)
+    gabs = oracle.vjp(og, unit, np.abs(g).astype(np.float64))
+    tol = 1e-5 * wabs + 1e-3 * gabs + 1e-8
+    err = np.abs(got - ref)
+    bad = err > tol
+    print(f"[grad] n={s['n']} disagree={s['disagree']} max_err={err.max():.3e} "
+          f"max_err/tol={(err / tol).max():.3f} nonzero={np.count_nonzero(ref)}", flush=True)
+    assert not bad.any(), np.argwhere(bad)[:10]
+    assert np.count_nonzero(ref) > 1000
+    return got, ref
+
+
+def test_backward_matches_oracle_vjp_tiny():
+    pt, scene, probes, views, grid, rad = _setup("tiny")
+    _check_grad(pt, probes, grid, rad, views[:1])
+
+
+def test_backward_matches_oracle_vjp_room_views():
+    pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=2, size=(96, 80))
+    _check_grad(pt, probes, grid, rad, views)
+
+
+def test_backward_accumulates():
+    pt, scene, probes, views, grid, rad = _setup("tiny")
+    rays = views[0].width * views[0].height
+    g = torch.ones((rays, 3), device="cuda")
+    a = torch.zeros((probes.n_probes, probes.N, probes.N, 3), device="cuda")
+    pt.probe_trace_backward(grid, views[:1], g, a)
+    b = a.clone()
+    pt.probe_trace_backward(grid, views[:1], g, b)
+    torch.testing.assert_close(b, 2 * a, rtol=1e-5, atol=1e-6)
+    # the total equals 3 x number of HIT rays (bilinear weights sum to one)
+    st = pt.probe_trace(grid, rad, views[:1])["status"]
+    assert abs(a.sum().item() - 3 * (st == 1).sum().item()) < 1e-2 * max(1, (st == 1).sum().item())
+
+
+def test_dot_product_identity_on_gpu():
+    pt, scene, probes, views, grid, rad = _setup("tiny")
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    x = torch.rand(rad.shape, generator=gen).to(torch.float16).cuda()
+    rays = views[0].width * views[0].height
+    y = torch.randn((rays, 3), generator=gen).cuda()
+    jx = pt.probe_trace(grid, x, views[:1])["rgb"]
+    jty = torch.zeros(rad.shape, dtype=torch.float32, device="cuda")
+    pt.probe_trace_backward(grid, views[:1], y, jty)
+    lhs = (jx.double() * y.double()).sum().item()
+    rhs = (x.double() * jty.double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-4 * max(1.0, abs(lhs))
+
+
+def test_autograd_function_and_finite_differences():
+    pt, scene, probes, views, grid, rad = _setup("tiny")
+    master = rad.float().clone().requires_grad_(True)
+    target = torch.rand((views[0].width * views[0].height, 3), device="cuda")
+    rgb = pt.ProbeTraceFn.apply(master, grid, views[:1])
+    loss = ((rgb - target) ** 2).sum()
+    loss.backward()
+    g = master.grad.clone()
+    # the function's gradient is probe_trace_backward of 2 (rgb - target)
+    ref = torch.zeros_like(g)
+    pt.probe_trace_backward(grid, views[:1], (2 * (rgb - target)).detach().contiguous(), ref)
+    torch.testing.assert_close(g, ref, rtol=1e-5, atol=1e-6)
+    # central differences on FP16 storage at the most influential texel-channels
+    flat = g.abs().flatten()
+    picks = torch.topk(flat, 6).indices.tolist()
+    h = 2.0 ** -6
+    base = torch.round(master.detach() * 256) / 256  # h-steps exact in FP16
+    for idx in picks:
+        vals = []
+        for s in (1, -1):
+            m = base.clone().flatten()
+            m[idx] += s * h
+            r = pt.probe_trace(grid, m.view_as(base).to(torch.float16), views[:1])["rgb"]
+            vals.append(((r.double() - target.double()) ** 2).sum().item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        r0 = pt.probe_trace(grid, base.to(torch.float16), views[:1])["rgb"]
+        gb = torch.zeros_like(g)
+        pt.probe_trace_backward(grid, views[:1], (2 * (r0 - target)).contiguous(), gb)
+        an = gb.flatten()[idx].item()
+        assert abs(fd - an) <= 2e-3 * max(1.0, abs(an)), (idx, fd, an)
+
+
+def test_adam_reduces_loss_on_small_differentiable_room():
+    pt = _pt()
+    scene, probes, views = workload("diff", N=32, levels=3, n_views=4, size=(64, 64))
+    target_scene = scene.with_albedos(4)
+    import synth
+    target_probes = synth.bake(target_scene, probes.N, probes.levels)
+    grid = pt.ProbeGrid.from_probes(probes)
+    trad = torch.from_numpy(target_probes.radiance.view(np.float16).copy()).cuda()
+    with torch.no_grad():
+        target = pt.probe_trace(grid, trad, views)["rgb"]
+    master = torch.full((probes.n_probes, probes.N, probes.N, 3), 0.5, device="cuda", requires_grad=True)
+    optim = torch.optim.Adam([master], lr=1e-2)
+    losses = []
+    for step in range(30):
+        optim.zero_grad()
+        rgb = pt.ProbeTraceFn.apply(master, grid, views)
+        loss = ((rgb - target) ** 2).mean()
+        loss.backward()
+        optim.step()
+        losses.append(loss.item())
+    assert losses[-1] < 0.5 * losses[0], losses
