@@ -152,10 +152,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single view 1920x1080; seeded room (seed 1) of 26 boxes/spheres; 8x8x4 probes, "
                                "128x128 octahedral maps (FP32 distance, FP16 normal/radiance), 5-level min pyramid",
-                   "rays_per_step": rays, "tile": [opts.tile_w, opts.tile_h], "start_level": opts.start_level},
+                   "rays_per_step": rays, "tile": [opts.tile_w, opts.tile_h], "start_level": opts.start_level,
+                   "launch": "persistent" if opts.flags & pt.PT_FLAG_PERSISTENT else "per-view"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "kernel": "k_trace_view", "algorithmic_bytes_per_launch": ab["total_bytes"],
+                     "kernel": "k_trace_persistent" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view",
+                     "algorithmic_bytes_per_launch": ab["total_bytes"],
                      "bytes_per_ray": ab["bytes_per_ray"]},
     }
     if not args.no_extras:
@@ -179,7 +181,7 @@ def main():
         bout = (torch.empty((brays, 3), device="cuda"), None, None, None)
         gopts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level,
                               flags=pt.PT_FLAG_GRAPH)
-        popts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level)
+        popts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level)  # one launch per view
         ms_g, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, gopts, out=bout), 3, 1, torch)
         ms_p, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, popts, out=bout), 3, 1, torch)
         result["batched"] = {"views": len(bviews), "rays": brays,

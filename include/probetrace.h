@@ -149,10 +149,12 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
                                const float *grad_rgb_dev, float *grad_radiance_dev, const pt_trace_opts *opts,
                                void *stream);
 
-/* Choose tile shape and pyramid start level for these views by timing candidate
- * launches on `stream` (synchronous; writes into the outputs, which must hold the views'
- * rays).  Results do not depend on the choice.  *opts is read for the algorithm constants
- * and receives tile_w, tile_h, start_level.  Errors: INVALID_ARGUMENT, HIP. */
+/* Choose tile shape, pyramid start level and launch form (per-view launches or one
+ * persistent launch; PT_FLAG_GRAPH is kept if the caller set it) for these views by timing
+ * candidate launches on `stream` (synchronous; writes into rgb_dev, which must hold the
+ * views' rays).  Results do not depend on the choice.  *opts is read for the algorithm
+ * constants and receives tile_w, tile_h, start_level and flags.  Errors: INVALID_ARGUMENT,
+ * HIP. */
 pt_status probe_autotune(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
                          int32_t n_views, float *rgb_dev, pt_trace_opts *opts, void *stream);
 

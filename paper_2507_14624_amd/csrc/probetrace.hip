@@ -16,6 +16,14 @@
 
 using namespace pt;
 
+// Minimum resident wavefronts per SIMD the trace kernels are compiled for (caps their
+// VGPR budget at 512 / PT_WAVES_PER_EU).  5 (96 VGPRs, a few bytes of spill) measured
+// fastest on the 1080p room against 4 (103 VGPRs) and 6 (80 VGPRs, more spill).
+#ifndef PT_WAVES_PER_EU
+#define PT_WAVES_PER_EU 5
+#endif
+#define PT_TRACE_KERNEL __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PT_WAVES_PER_EU)))
+
 // ------------------------------------------------------------------------------------
 // errors
 // ------------------------------------------------------------------------------------
@@ -43,6 +51,7 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     std::vector<unsigned char> key;
     ViewDev *views_dev = nullptr;
+    uint32_t *cage = nullptr;       // cage-order table of the captured views
     int cap = 0;
     hipStream_t capture = nullptr;  // private stream the graph is captured on
 };
@@ -60,6 +69,10 @@ struct pt_grid {
     int views_cap = 0;
     hipEvent_t staging_free = nullptr;
     int *counter = nullptr;
+    // per-view cage-order tables: [views][cells] packed corner codes
+    uint32_t *cage = nullptr;
+    int64_t cage_cap = 0;
+    int cells = 0;
     GraphCache graph;
     int num_cus = 256;
 };
@@ -147,7 +160,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     g->P = (int)P;
     g->N = N;
     g->L = L;
-    g->stride = (int64_t)level_offset(N, L);
+    g->stride = 2 * (int64_t)N * N;
+    g->cells = (desc->dims[0] - 1) * (desc->dims[1] - 1) * (desc->dims[2] - 1);
     hipStream_t s = (hipStream_t)stream;
     auto cleanup = [&](pt_status st, const std::string &m) {
         probe_grid_destroy(g);
@@ -182,6 +196,8 @@ extern "C" void probe_grid_destroy(pt_grid *g) {
     if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
     if (g->graph.graph) (void)hipGraphDestroy(g->graph.graph);
     if (g->graph.views_dev) (void)hipFree(g->graph.views_dev);
+    if (g->graph.cage) (void)hipFree(g->graph.cage);
+    if (g->cage) (void)hipFree(g->cage);
     if (g->graph.capture) (void)hipStreamDestroy(g->graph.capture);
     if (g->pyr) (void)hipFree(g->pyr);
     if (g->nrm) (void)hipFree(g->nrm);
@@ -240,9 +256,21 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + min(x, rem) + slot;
 }
 
+// Cage order of every cell for every view (the eye is the same for all rays of a view).
+__global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single, int n_views, int cells,
+                             uint32_t *__restrict__ tab) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_views * cells) return;
+    int v = (int)(i / cells), c = (int)(i % cells);
+    const float *X = views ? views[v].pos : single.pos;
+    int nx = g.n[0] - 1, ny = g.n[1] - 1;
+    int cell[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+    tab[i] = cage_order(g, cell, X);
+}
+
 // One view: each wavefront owns one tw x th pixel tile.
-__global__ void __launch_bounds__(256) k_trace_view(GridDev g, ViewDev v, const uint16_t *__restrict__ rad,
-                                                    Outputs o, int tw, int th) {
+PT_TRACE_KERNEL k_trace_view(GridDev g, ViewDev v, const uint32_t *__restrict__ cage,
+                                                    const uint16_t *__restrict__ rad, Outputs o, int tw, int th) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int nb = gridDim.x;
     int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
@@ -254,11 +282,11 @@ __global__ void __launch_bounds__(256) k_trace_view(GridDev g, ViewDev v, const 
     float w[3];
     camera_ray(v, x, y, w);
     RayResult r;
-    trace_ray(g, v.pos, w, r);
+    trace_ray(g, v.pos, w, cage, r);
     write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
 }
 
-__global__ void __launch_bounds__(256) k_trace_rays(GridDev g, const float *__restrict__ orig,
+PT_TRACE_KERNEL k_trace_rays(GridDev g, const float *__restrict__ orig,
                                                     const float *__restrict__ dirs, int64_t n,
                                                     const uint16_t *__restrict__ rad, Outputs o) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,7 +303,7 @@ __global__ void __launch_bounds__(256) k_trace_rays(GridDev g, const float *__re
     } else {
         float inv = 1.0f / sqrtf(l2);
         float w[3] = {d[0] * inv, d[1] * inv, d[2] * inv};
-        trace_ray(g, X, w, r);
+        trace_ray(g, X, w, nullptr, r);
     }
     write_result(g, rad, r, i, o);
 }
@@ -284,7 +312,8 @@ __global__ void __launch_bounds__(256) k_trace_rays(GridDev g, const float *__re
 // queue is empty (every wave reaches that exit).
 __global__ void k_reset_counter(int *c) { c[0] = 0; }
 
-__global__ void __launch_bounds__(256) k_trace_persistent(GridDev g, const ViewDev *__restrict__ views, int n_views,
+PT_TRACE_KERNEL k_trace_persistent(GridDev g, const ViewDev *__restrict__ views, int n_views,
+                                                          const uint32_t *__restrict__ cage, int cells,
                                                           int total_tiles, int *counter,
                                                           const uint16_t *__restrict__ rad, Outputs o, int tw,
                                                           int th) {
@@ -309,43 +338,92 @@ __global__ void __launch_bounds__(256) k_trace_persistent(GridDev g, const ViewD
             float w[3];
             camera_ray(v, x, y, w);
             RayResult r;
-            trace_ray(g, v.pos, w, r);
+            trace_ray(g, v.pos, w, cage + (int64_t)lo * cells, r);
             write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
         }
     }
 }
 
+// Wavefront-segmented scatter-add.  Every lane holds up to 4 (key, rgb) contributions
+// (key = texel-channel base index, -1 = none).  Per distinct key present in the wave, the
+// lanes holding it add their contributions with a butterfly reduction and one lane issues
+// the three FP32 atomics, so a wave touching k distinct texels issues 3k atomics instead
+// of 12 per lane.  All 64 lanes must arrive here together.
+__device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const int64_t key[4],
+                                                 const float val[4][3]) {
+    const int lane = threadIdx.x & 63;
+    bool pend[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pend[k] = key[k] >= 0;
+    for (int guard = 0; guard < 256; ++guard) {
+        bool any = pend[0] | pend[1] | pend[2] | pend[3];
+        unsigned long long m = __ballot(any);
+        if (m == 0ull) break;
+        int leader = __ffsll(m) - 1;
+        int64_t mine = pend[0] ? key[0] : (pend[1] ? key[1] : (pend[2] ? key[2] : key[3]));
+        int lo = __shfl((int)(mine & 0xffffffff), leader, 64);
+        int hi = __shfl((int)(mine >> 32), leader, 64);
+        int64_t lkey = ((int64_t)hi << 32) | (uint32_t)lo;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            bool take = pend[k] && key[k] == lkey;
+            s0 += take ? val[k][0] : 0.0f;
+            s1 += take ? val[k][1] : 0.0f;
+            s2 += take ? val[k][2] : 0.0f;
+            pend[k] = pend[k] && !take;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+        }
+        if (lane == leader) {
+            atomicAdd(grad + lkey + 0, s0);
+            atomicAdd(grad + lkey + 1, s1);
+            atomicAdd(grad + lkey + 2, s2);
+        }
+    }
+}
+
 // Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
-__global__ void __launch_bounds__(256) k_backward_view(GridDev g, ViewDev v, const float *__restrict__ grad_rgb,
+PT_TRACE_KERNEL k_backward_view(GridDev g, ViewDev v, const uint32_t *__restrict__ cage,
+                                                       const float *__restrict__ grad_rgb,
                                                        float *__restrict__ grad_rad, int tw, int th) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int nb = gridDim.x;
     int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
     int tiles_y = (v.H + th - 1) / th;
-    if (tile >= v.tiles_x * tiles_y) return;
+    if (tile >= v.tiles_x * tiles_y) return;  // whole wavefronts only
     int x = (tile % v.tiles_x) * tw + lane % tw;
     int y = (tile / v.tiles_x) * th + lane / tw;
-    if (x >= v.W || y >= v.H) return;
-    float w[3];
-    camera_ray(v, x, y, w);
-    RayResult r;
-    trace_ray(g, v.pos, w, r);
-    if (r.status != ST_HIT) return;
-    int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
-    float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
-    float u, vv;
-    oct_encode(r.q[0], r.q[1], r.q[2], u, vv);
-    int idx[4];
-    float wt[4];
-    bilinear_taps(u, vv, g.N, idx, wt);
-    float *G = grad_rad + (int64_t)r.probe * g.N * g.N * 3;
+    int64_t key[4] = {-1, -1, -1, -1};
+    float val[4][3] = {};
+    if (x < v.W && y < v.H) {
+        float w[3];
+        camera_ray(v, x, y, w);
+        RayResult r;
+        trace_ray(g, v.pos, w, cage, r);
+        if (r.status == ST_HIT) {
+            int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
+            float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
+            float u, vv;
+            oct_encode(r.q[0], r.q[1], r.q[2], u, vv);
+            int idx[4];
+            float wt[4];
+            bilinear_taps(u, vv, g.N, idx, wt);
+            int64_t base = (int64_t)r.probe * g.N * g.N;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (wt[k] == 0.0f) continue;
-        atomicAdd(G + 3 * idx[k] + 0, wt[k] * gr[0]);
-        atomicAdd(G + 3 * idx[k] + 1, wt[k] * gr[1]);
-        atomicAdd(G + 3 * idx[k] + 2, wt[k] * gr[2]);
+            for (int k = 0; k < 4; ++k) {
+                if (wt[k] != 0.0f) key[k] = 3 * (base + idx[k]);
+                val[k][0] = wt[k] * gr[0];
+                val[k][1] = wt[k] * gr[1];
+                val[k][2] = wt[k] * gr[2];
+            }
+        }
     }
+    wave_scatter_add(grad_rad, key, val);
 }
 
 // ------------------------------------------------------------------------------------
@@ -360,6 +438,7 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
         d.n[a] = g->desc.dims[a];
         d.org[a] = g->desc.origin[a];
         d.spc[a] = g->desc.spacing[a];
+        d.ispc[a] = 1.0f / g->desc.spacing[a];
         d.smin[a] = g->desc.scene_min[a];
         d.smax[a] = g->desc.scene_max[a];
         d.bg[a] = o.background[a];
@@ -453,11 +532,28 @@ static pt_status upload_views(pt_grid *g, const std::vector<ViewDev> &vd, hipStr
 
 static unsigned persistent_blocks(const pt_grid *g) { return (unsigned)(g->num_cus * 8); }
 
-static pt_status launch_persistent(pt_grid *g, const GridDev &d, const ViewDev *views_dev, int n_views, int tiles,
-                                   const uint16_t *rad, const Outputs &o, int tw, int th, hipStream_t s) {
+// grow a device buffer of `cap` elements (synchronises `s` before freeing the old one)
+template <typename T>
+static pt_status ensure_device(T *&buf, int64_t &cap, int64_t need, hipStream_t s, const char *what) {
+    if (need <= cap) return PT_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (buf) HIP_TRY(hipFree(buf));
+    buf = nullptr;
+    cap = 0;
+    if (hipMalloc(&buf, sizeof(T) * need) != hipSuccess) return fail(PT_ERR_OUT_OF_MEMORY, what);
+    cap = need;
+    return PT_OK;
+}
+
+static pt_status launch_persistent(pt_grid *g, const GridDev &d, const ViewDev *views_dev, uint32_t *cage,
+                                   int n_views, int tiles, const uint16_t *rad, const Outputs &o, int tw, int th,
+                                   hipStream_t s) {
+    int64_t nc = (int64_t)n_views * g->cells;
+    hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, d, views_dev, ViewDev{}, n_views,
+                       g->cells, cage);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g->counter);
-    hipLaunchKernelGGL(k_trace_persistent, dim3(persistent_blocks(g)), dim3(256), 0, s, d, views_dev, n_views, tiles,
-                       g->counter, rad, o, tw, th);
+    hipLaunchKernelGGL(k_trace_persistent, dim3(persistent_blocks(g)), dim3(256), 0, s, d, views_dev, n_views, cage,
+                       g->cells, tiles, g->counter, rad, o, tw, th);
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }
@@ -491,9 +587,14 @@ static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewD
         if (n > gc.cap) {
             HIP_TRY(hipStreamSynchronize(s));
             if (gc.views_dev) HIP_TRY(hipFree(gc.views_dev));
+            if (gc.cage) HIP_TRY(hipFree(gc.cage));
             gc.views_dev = nullptr;
+            gc.cage = nullptr;
+            gc.cap = 0;
             if (hipMalloc(&gc.views_dev, sizeof(ViewDev) * n) != hipSuccess)
                 return fail(PT_ERR_OUT_OF_MEMORY, "graph view table allocation");
+            if (hipMalloc(&gc.cage, sizeof(uint32_t) * (size_t)n * std::max(1, g->cells)) != hipSuccess)
+                return fail(PT_ERR_OUT_OF_MEMORY, "graph cage table allocation");
             gc.cap = n;
         }
         // the table is baked into this graph: copy it now, outside the capture
@@ -503,7 +604,7 @@ static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewD
         // stream, which cannot capture); the graph is then launched on the caller's stream
         if (!gc.capture) HIP_TRY(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal));
-        pt_status st = launch_persistent(g, d, gc.views_dev, n, tiles, rad, o, tw, th, gc.capture);
+        pt_status st = launch_persistent(g, d, gc.views_dev, gc.cage, n, tiles, rad, o, tw, th, gc.capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(gc.capture, &graph);
         if (st != PT_OK) {
@@ -534,15 +635,20 @@ static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_vie
     make_griddev(g, opts, d);
     uint32_t flags = opts ? opts->flags : 0;
     if (flags & PT_FLAG_GRAPH) return run_graph(g, d, vd, tiles, rad, o, tw, th, s);
+    st = ensure_device(g->cage, g->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
+    if (st != PT_OK) return st;
     if (flags & PT_FLAG_PERSISTENT) {
         st = upload_views(g, vd, s);
         if (st != PT_OK) return st;
-        return launch_persistent(g, d, g->views_dev, n_views, tiles, rad, o, tw, th, s);
+        return launch_persistent(g, d, g->views_dev, g->cage, n_views, tiles, rad, o, tw, th, s);
     }
     for (int i = 0; i < n_views; ++i) {
         int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
         unsigned nb = (unsigned)((vt + 3) / 4);
-        hipLaunchKernelGGL(k_trace_view, dim3(nb), dim3(256), 0, s, d, vd[i], rad, o, tw, th);
+        uint32_t *cage = g->cage + (int64_t)i * g->cells;
+        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(g->cells, 256)), dim3(256), 0, s, d, nullptr, vd[i], 1,
+                           g->cells, cage);
+        hipLaunchKernelGGL(k_trace_view, dim3(nb), dim3(256), 0, s, d, vd[i], cage, rad, o, tw, th);
     }
     HIP_TRY(hipGetLastError());
     return PT_OK;
@@ -589,11 +695,17 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
     GridDev d;
     make_griddev(g, opts, d);
     hipStream_t s = (hipStream_t)stream;
+    pt_grid *mg = const_cast<pt_grid *>(g);
+    st = ensure_device(mg->cage, mg->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
+    if (st != PT_OK) return st;
     for (int i = 0; i < n_views; ++i) {
         int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
         unsigned nb = (unsigned)((vt + 3) / 4);
-        hipLaunchKernelGGL(k_backward_view, dim3(nb), dim3(256), 0, s, d, vd[i], grad_rgb_dev, grad_radiance_dev, tw,
-                           th);
+        uint32_t *cage = mg->cage + (int64_t)i * g->cells;
+        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(g->cells, 256)), dim3(256), 0, s, d, nullptr, vd[i], 1,
+                           g->cells, cage);
+        hipLaunchKernelGGL(k_backward_view, dim3(nb), dim3(256), 0, s, d, vd[i], cage, grad_rgb_dev,
+                           grad_radiance_dev, tw, th);
     }
     HIP_TRY(hipGetLastError());
     return PT_OK;
@@ -611,34 +723,42 @@ extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_d
     float best = INFINITY;
     pt_trace_opts bo = *opts;
     Outputs o{rgb_dev, nullptr, nullptr, nullptr};
+    pt_status st = PT_OK;
+    // candidates: tile shape x pyramid start level x (per-view launches | one persistent
+    // launch); the graph flag, if set by the caller, is kept
     for (auto &sh : shapes) {
-        for (int lv = g->L - 1; lv >= std::max(0, g->L - 3); --lv) {
-            pt_trace_opts c = *opts;
-            c.tile_w = sh[0];
-            c.tile_h = sh[1];
-            c.start_level = lv;
-            pt_status st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);  // warm-up
-            if (st != PT_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            HIP_TRY(hipEventRecord(e0, s));
-            for (int r = 0; r < 3; ++r) trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bo = c;
+        for (int lv = g->L - 1; lv >= std::max(0, g->L - 3) && st == PT_OK; --lv) {
+            for (int persistent = 0; persistent < 2 && st == PT_OK; ++persistent) {
+                pt_trace_opts c = *opts;
+                c.tile_w = sh[0];
+                c.tile_h = sh[1];
+                c.start_level = lv;
+                c.flags = (opts->flags & ~PT_FLAG_PERSISTENT) | (persistent ? PT_FLAG_PERSISTENT : 0u);
+                if (c.flags & PT_FLAG_GRAPH) c.flags &= ~PT_FLAG_PERSISTENT;  // the graph is persistent
+                st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);  // warm-up
+                if (st != PT_OK) break;
+                if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PT_ERR_HIP, "hipEventRecord"); break; }
+                for (int r = 0; r < 3 && st == PT_OK; ++r) st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
+                if (st != PT_OK) break;
+                float ms = 0;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = fail(PT_ERR_HIP, "autotune timing");
+                    break;
+                }
+                if (ms < best) {
+                    best = ms;
+                    bo = c;
+                }
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (st != PT_OK) return st;
     opts->tile_w = bo.tile_w;
     opts->tile_h = bo.tile_h;
     opts->start_level = bo.start_level;
+    opts->flags = bo.flags;
     return PT_OK;
 }

@@ -24,9 +24,10 @@ struct GridDev {
     int n[3];        // probes per axis
     float org[3];    // probe (0,0,0)
     float spc[3];    // spacing
+    float ispc[3];   // 1 / spacing
     float smin[3], smax[3];
     int N;           // level-0 map resolution (power of two)
-    int logN;
+    int logN;        // log2(N)
     int L;           // pyramid levels
     int top;         // level the march starts at
     int P;           // number of probes
@@ -39,10 +40,12 @@ struct GridDev {
     int max_probes;
 };
 
-// Offset of level l inside a probe block: sum_{m<l} (N>>m)^2 = 4 (N^2 - (N>>l)^2) / 3.
+// Offset of level l inside a probe block: 2 (N^2 - (N>>l)^2).  The gap between levels l and
+// l+1 is 1.5 (N>>l)^2 >= (N>>l)^2, so every level fits, the block is 2 N^2 floats, and
+// the offset needs only shifts (no integer multiply or divide in the march).
 __host__ __device__ __forceinline__ int level_offset(int N, int l) {
-    int nl = N >> l;
-    return (4 * (N * N - nl * nl)) / 3;
+    int NN = N * N;
+    return 2 * (NN - (NN >> (2 * l)));
 }
 
 // grid plane / probe coordinate along axis a (shared by the cell iterator and the probes)
@@ -50,8 +53,13 @@ __device__ __forceinline__ float grid_coord(const GridDev &g, int a, int idx) {
     return __fmaf_rn((float)idx, g.spc[a], g.org[a]);
 }
 
-// ray parameter where coordinate a reaches `plane` (shared by cell walls and octant cuts)
-__device__ __forceinline__ float plane_t(float plane, float x, float w) { return (plane - x) / w; }
+// Reciprocal (hardware v_rcp_f32, 1 ulp).  Every quantity the march compares is always
+// produced by the same inline expression, so its value is reproducible bit for bit.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ray parameter where coordinate a reaches `plane` (shared by cell walls and octant cuts;
+// iw = 1/w of that axis)
+__device__ __forceinline__ float plane_t(float plane, float x, float iw) { return (plane - x) * iw; }
 
 __device__ __forceinline__ float sgnp(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
 
@@ -59,7 +67,7 @@ __device__ __forceinline__ float half_bits(uint16_t b) { return __half2float(__u
 
 // Octahedral encode (z fold axis), returns (u, v) in [-1, 1]^2.
 __device__ __forceinline__ void oct_encode(float x, float y, float z, float &u, float &v) {
-    float inv = 1.0f / (fabsf(x) + fabsf(y) + fabsf(z));
+    float inv = frcp(fabsf(x) + fabsf(y) + fabsf(z));
     float px = x * inv, py = y * inv, pz = z * inv;
     if (pz >= 0.0f) {
         u = px;
@@ -136,7 +144,7 @@ __device__ __forceinline__ float cross_t(int c, int dir, float P0, float P1, flo
     float fc = (float)c;
     float den = __fmaf_rn(-fc, L1, P1);
     float num = __fmaf_rn(fc, L0, -P0);
-    return ((float)dir * den > 0.0f) ? num / den : INFINITY;
+    return ((float)dir * den > 0.0f) ? num * frcp(den) : INFINITY;
 }
 
 __device__ __forceinline__ float next_x(const Piece &s, int I, int l) {
@@ -188,8 +196,9 @@ __device__ __forceinline__ void piece_xy(const Piece &s, const float Xp[3], cons
     L = __fmaf_rn(t, s.L1, s.L0);
     float A = __fmaf_rn(t, s.A1, s.A0);
     float B = __fmaf_rn(t, s.B1, s.B0);
-    x = A / L;
-    y = B / L;
+    float iL = frcp(L);
+    x = A * iL;
+    y = B * iL;
 }
 
 struct Fire {
@@ -217,68 +226,64 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
     int l = g.top;
     int I = i0 >> l, J = j0 >> l;
     int off = level_offset(N, l);
+    const int last = (int)g.stride - 1;
     float t = s.ts;
     float rc2 = rho2_at(Xp, w, t);
     float tx = next_x(s, I, l), ty = next_y(s, J, l);
     const int guard = 24 * N + 64;
     for (int it = 0; it < guard; ++it) {
-        float tmin = fminf(tx, ty);
-        float texit = fmaxf(fminf(tmin, s.te), t);
+        // selects, not fminf/fmaxf: the candidates are never NaN and selects need no
+        // NaN canonicalisation
+        float tmin = tx < ty ? tx : ty;
+        float tend = tmin < s.te ? tmin : s.te;
+        float texit = tend > t ? tend : t;
         float re2 = rho2_at(Xp, w, texit);
-        float m2 = fmaxf(rc2, re2);
-        int nl = N >> l;
-        float M = blk[off + J * nl + I];
+        float m2 = rc2 > re2 ? rc2 : re2;
+        // the index stays inside the probe block even if the walk were wrong
+        float M = blk[min(off + (J << (g.logN - l)) + I, last)];
         // coarse levels test conservatively (the min over a parent must not miss a child
         // whose ray span's rho^2 rounds a little above the parent's endpoints)
         float lim = l == 0 ? m2 : m2 * 1.0000153f;
-        bool fire = (M < 0.0f) || (M * M < lim);
+        bool fire = (M < 0.0f) | (M * M < lim);
+        if (fire && l == 0) {
+            f.i = I;
+            f.j = J;
+            f.tin = t;
+            f.rin2 = rc2;
+            return true;
+        }
+        if (!fire && !(tmin < s.te)) return false;  // the piece ends inside this texel
         if (fire) {
-            if (l == 0) {
-                f.i = I;
-                f.j = J;
-                f.tin = t;
-                f.rin2 = rc2;
-                return true;
-            }
             // descend into the child that holds the ray point at t
             float x, y, Lt;
             piece_xy(s, Xp, w, t, N, x, y, Lt);
             --l;
-            float sc = 1.0f / (float)(1 << l);
+            off = level_offset(N, l);
+            float sc = __builtin_ldexpf(1.0f, -l);
             int ci = (int)floorf(x * sc), cj = (int)floorf(y * sc);
             ci = min(max(ci, 2 * I), 2 * I + 1);
             cj = min(max(cj, 2 * J), 2 * J + 1);
             I = min(max(ci, s.ilo >> l), s.ihi >> l);
             J = min(max(cj, s.jlo >> l), s.jhi >> l);
-            off = level_offset(N, l);
-            tx = next_x(s, I, l);
-            ty = next_y(s, J, l);
-            continue;
-        }
-        if (!(tmin < s.te)) return false;  // the piece ends inside this texel
-        bool stepx = tx == tmin, stepy = ty == tmin;
-        int Io = I, Jo = J;
-        t = texit;
-        rc2 = re2;
-        if (stepx) I = min(max(I + s.dx, s.ilo >> l), s.ihi >> l);
-        if (stepy) J = min(max(J + s.dy, s.jlo >> l), s.jhi >> l);
-        bool up = false;
-        while (l < g.top && (((I >> 1) != (Io >> 1)) || ((J >> 1) != (Jo >> 1)))) {
-            I >>= 1;
-            J >>= 1;
-            Io >>= 1;
-            Jo >>= 1;
-            ++l;
-            up = true;
-        }
-        if (up) {
-            off = level_offset(N, l);
-            tx = next_x(s, I, l);
-            ty = next_y(s, J, l);
         } else {
-            if (stepx) tx = next_x(s, I, l);
-            if (stepy) ty = next_y(s, J, l);
+            // step past the texel; a finite candidate implies the crossed boundary lies
+            // inside the quadrant, so the stepped index stays in range.  Move up while the
+            // step left the parent: the parents differ at every shift up to the highest
+            // bit in which the old and new indices differ.
+            int In = I + (tx == tmin ? s.dx : 0);
+            int Jn = J + (ty == tmin ? s.dy : 0);
+            int diff = (In ^ I) | (Jn ^ J);
+            int h = 31 - __builtin_clz((unsigned)diff | 1u);
+            int up = min(h, g.top - l);
+            I = In >> up;
+            J = Jn >> up;
+            l += up;
+            off = level_offset(N, l);
+            t = texit;
+            rc2 = re2;
         }
+        tx = next_x(s, I, l);
+        ty = next_y(s, J, l);
     }
     return false;
 }
@@ -291,8 +296,8 @@ struct ProbeResult {
 };
 
 // traceOneProbe over [ta, tb] for probe (pi, pj, pk).
-__device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const float X[3], const float w[3], float ta,
-                            float tb, ProbeResult &res) {
+__device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const float X[3], const float w[3],
+                            const float iw[3], float ta, float tb, ProbeResult &res) {
     const int N = g.N;
     const int p = pi + g.n[0] * (pj + g.n[1] * pk);
     float O[3] = {grid_coord(g, 0, pi), grid_coord(g, 1, pj), grid_coord(g, 2, pk)};
@@ -323,7 +328,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (w[a] != 0.0f) {
-            float tz = plane_t(O[a], X[a], w[a]);
+            float tz = plane_t(O[a], X[a], iw[a]);
             if (tz > ta && tz < tb) {
                 // insert into the sorted triple
                 if (tz < c0) {
@@ -401,18 +406,58 @@ struct RayResult {
 
 // One camera ray (X, w unit): grid iterator over cells, 8 cage probes closest to the eye
 // first, fall-through on MISS and UNKNOWN.
-__device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], RayResult &out) {
+// cage order of one cell: the 8 corner codes (dx + 2 dy + 4 dz) sorted by squared distance
+// of the corner probe to the eye, ties by code, packed 3 bits each (first probe lowest)
+__device__ __forceinline__ uint32_t cage_order(const GridDev &g, const int cell[3], const float X[3]) {
+    float key[8];
+    int code[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float dx = grid_coord(g, 0, cell[0] + (c & 1)) - X[0];
+        float dy = grid_coord(g, 1, cell[1] + ((c >> 1) & 1)) - X[1];
+        float dz = grid_coord(g, 2, cell[2] + (c >> 2)) - X[2];
+        key[c] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+        code[c] = c;
+    }
+    // insertion sort, fully unrolled (stable: equal keys keep corner-code order)
+#pragma unroll
+    for (int a = 1; a < 8; ++a) {
+#pragma unroll
+        for (int b = a; b > 0; --b) {
+            bool sw = key[b] < key[b - 1];
+            float k0 = key[b - 1], k1 = key[b];
+            int c0 = code[b - 1], c1 = code[b];
+            key[b - 1] = sw ? k1 : k0;
+            key[b] = sw ? k0 : k1;
+            code[b - 1] = sw ? c1 : c0;
+            code[b] = sw ? c0 : c1;
+        }
+    }
+    uint32_t packed = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) packed |= (uint32_t)code[c] << (3 * c);
+    return packed;
+}
+
+__device__ __forceinline__ int cell_index(const GridDev &g, const int cell[3]) {
+    return cell[0] + (g.n[0] - 1) * (cell[1] + (g.n[1] - 1) * cell[2]);
+}
+
+// cage: optional per-view table of cage_order() for every cell (same eye for all rays).
+__device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], const uint32_t *__restrict__ cage,
+                          RayResult &out) {
     out.status = ST_MISS;
     out.probe = -1;
     out.texel = -1;
     out.t = INFINITY;
+    const float iw[3] = {frcp(w[0]), frcp(w[1]), frcp(w[2])};
     // until the ray leaves the scene box (slightly enlarged)
     float tfar = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float t = INFINITY;
-        if (w[a] > 0.0f) t = plane_t(g.smax[a], X[a], w[a]);
-        else if (w[a] < 0.0f) t = plane_t(g.smin[a], X[a], w[a]);
+        if (w[a] > 0.0f) t = plane_t(g.smax[a], X[a], iw[a]);
+        else if (w[a] < 0.0f) t = plane_t(g.smin[a], X[a], iw[a]);
         tfar = fminf(tfar, t);
     }
     tfar = tfar * 1.0001f;
@@ -420,7 +465,7 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
     int cell[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float q = (X[a] - g.org[a]) / g.spc[a];
+        float q = (X[a] - g.org[a]) * g.ispc[a];
         cell[a] = min(max((int)floorf(q), 0), g.n[a] - 2);
     }
     bool any_unknown = false;
@@ -433,41 +478,15 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
             int pidx = -1;
             if (w[a] > 0.0f && cell[a] + 1 <= g.n[a] - 2) pidx = cell[a] + 1;
             else if (w[a] < 0.0f && cell[a] >= 1) pidx = cell[a];
-            tn[a] = pidx >= 0 ? plane_t(grid_coord(g, a, pidx), X[a], w[a]) : INFINITY;
+            tn[a] = pidx >= 0 ? plane_t(grid_coord(g, a, pidx), X[a], iw[a]) : INFINITY;
         }
         float tb = fminf(fminf(fminf(tn[0], tn[1]), tn[2]), tfar);
-        // cage order: squared distance to the eye, ties by corner code
-        float key[8];
-        int code[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            float dx = grid_coord(g, 0, cell[0] + (c & 1)) - X[0];
-            float dy = grid_coord(g, 1, cell[1] + ((c >> 1) & 1)) - X[1];
-            float dz = grid_coord(g, 2, cell[2] + (c >> 2)) - X[2];
-            key[c] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-            code[c] = c;
-        }
-        // insertion sort, fully unrolled (stable: equal keys keep corner-code order)
-#pragma unroll
-        for (int a = 1; a < 8; ++a) {
-#pragma unroll
-            for (int b = a; b > 0; --b) {
-                bool sw = key[b] < key[b - 1];
-                float k0 = key[b - 1], k1 = key[b];
-                int c0 = code[b - 1], c1 = code[b];
-                key[b - 1] = sw ? k1 : k0;
-                key[b] = sw ? k0 : k1;
-                code[b - 1] = sw ? c1 : c0;
-                code[b] = sw ? c0 : c1;
-            }
-        }
+        uint32_t order = cage ? cage[cell_index(g, cell)] : cage_order(g, cell, X);
         for (int rk = 0; rk < g.max_probes; ++rk) {
-            int c = code[0];
-            // rotate the next code into slot 0 without dynamic register indexing
-#pragma unroll
-            for (int m = 0; m < 7; ++m) code[m] = code[m + 1];
+            int c = (int)(order & 7u);
+            order >>= 3;
             ProbeResult pr;
-            trace_probe(g, cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2), X, w, ta, tb, pr);
+            trace_probe(g, cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2), X, w, iw, ta, tb, pr);
             if (pr.status == ST_HIT) {
                 out.status = ST_HIT;
                 out.probe = (cell[0] + (c & 1)) + g.n[0] * ((cell[1] + ((c >> 1) & 1)) + g.n[1] * (cell[2] + (c >> 2)));

@@ -143,11 +143,15 @@ def test_parity_arbitrary_rays_and_probe_centres():
     o = o[[synth.clearance(scene, x) > 0.01 for x in o]][:n].astype(np.float32)
     n = len(o)
     d = rng.normal(size=(n, 3)).astype(np.float32)
-    # rays from every probe centre (eye aligned with the probe)
+    # rays from every probe centre through texel centres (eye aligned with the probe)
     P = probes.n_probes
+    N = probes.N
     po = np.stack([og.probe_position(p) for p in range(P)]).astype(np.float32)
+    ks = rng.choice(N * N, size=(P, 64))
+    c = -1 + (2 * np.arange(N) + 1) / N
+    de = np.array([oracle.oct_decode(np.array([c[k % N], c[k // N]])) for k in ks.ravel()]).astype(np.float32)
     o = np.concatenate([o, np.repeat(po, 64, axis=0)])
-    d = np.concatenate([d, rng.normal(size=(P * 64, 3)).astype(np.float32)])
+    d = np.concatenate([d, de])
     o[5], d[5] = o[4], 0.0  # degenerate direction
     res = _gpu_numpy(pt.probe_trace_rays(grid, rad, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()))
     keep = np.ones(len(o), bool)
@@ -156,7 +160,10 @@ def test_parity_arbitrary_rays_and_probe_centres():
     assert_parity(compare(res, orc, sel=keep), "arbitrary rays")
     assert res["status"][5] == oracle.MISS and np.isinf(res["t"][5])
     eye = np.arange(n, len(o))
+    pe = np.repeat(np.arange(P), 64)
     assert np.all(res["status"][eye] == oracle.HIT)
+    assert np.array_equal(res["hit"][eye, 0], pe) and np.array_equal(res["hit"][eye, 1], ks.ravel())
+    assert np.array_equal(res["t"][eye], probes.distance.reshape(P, -1)[pe, ks.ravel()])
 
 
 def test_parity_options():
