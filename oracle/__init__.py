@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("status", "t", "rgb", "probe", "texel", "margin", "tests", "normals", "flat_tests", "rank",
-                 "taps", "wts", "score")]
+                 "taps", "wts", "score", "work")]
 
 
 def build_native(force: bool = True) -> str:
@@ -212,8 +212,9 @@ def default_opts(N: int, **kw) -> dict:
 
 def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, **kw) -> dict:
     """Trace rays; returns per-ray arrays (status, t, rgb, probe, texel, margin, tests,
-    normals, flat_tests, rank, taps, wts, score).  ``score`` is the smallest gap/error-scale
-    ratio over the ray's decisions; ``margin`` has a bit per decision kind with ratio <= delta."""
+    normals, flat_tests, rank, taps, wts, score, work).  ``score`` is the smallest gap/error-scale
+    ratio over the ray's decisions; ``margin`` has a bit per decision kind with ratio <= delta;
+    ``work`` counts probe traces, pieces marched and cells visited."""
     lib = _load()
     o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
@@ -232,7 +233,7 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, **kw) -> dict:
                probe=np.empty(n, np.int32), texel=np.empty(n, np.int32), margin=np.empty(n, np.int32),
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),
                rank=np.empty(n, np.int32), taps=np.empty((n, 4), np.int32), wts=np.empty((n, 4), np.float64),
-               score=np.empty(n, np.float64))
+               score=np.empty(n, np.float64), work=np.empty((n, 3), np.int32))
     out = _Out()
     for k, v in res.items():
         setattr(out, k, v.ctypes.data)
@@ -310,6 +311,30 @@ def bilinear_taps(u: float, v: float, N: int):
 
 def half_to_double(h: int) -> float:
     return float(_load().oracle_half_to_double(int(h)))
+
+
+# FP32 operations of one step of the reference schedule (an FMA counts 2, a compare,
+# min/max or reciprocal 1):
+#   texel test: ray point at the texel exit (3 FMA = 6), squared radial distance (mul +
+#     2 FMA = 5), max with the entry value (1), stored value squared and compare (2), next
+#     boundary crossing (2 FMA + reciprocal + mul + sign test = 8), min of candidates (2)
+#   piece: six linear forms (6 x 5), two motion signs (2 x 3), start texel (3 FMA +
+#     reciprocal + 2 mul = 9), two first crossings (2 x 8)
+#   probe trace: probe position (3 FMA = 6), relative origin (3), its squared length (5),
+#     three octant cuts (3 x 2)
+#   cell: three plane crossings (3 x 2) and their minimum (3)
+#   HIT: normal decode and facing test (11), larger root (20), hit direction encode (8),
+#     bilinear weights (10), 4 taps x 3 channels FMA (24)
+#   ray: pinhole direction (25), scene-box exit (9)
+FLOPS = dict(test=24, piece=61, probe=20, cell=9, hit=73, ray=34)
+
+
+def algorithmic_flops(result: dict) -> np.ndarray:
+    """Per-ray FP32 operations of the reference schedule (FLOPS table x the oracle's counts)."""
+    w = result["work"].astype(np.int64)
+    return (FLOPS["test"] * result["tests"].astype(np.int64) + FLOPS["piece"] * w[:, 1]
+            + FLOPS["probe"] * w[:, 0] + FLOPS["cell"] * w[:, 2]
+            + FLOPS["hit"] * (result["status"] == HIT).astype(np.int64) + FLOPS["ray"])
 
 
 def algorithmic_bytes(result: dict) -> np.ndarray:

@@ -104,6 +104,7 @@ typedef struct {
     int32_t *taps;     /* [n][4] radiance tap texel indices (-1 for non-HIT) */
     double *wts;       /* [n][4] bilinear weights */
     double *score;     /* [n] min over decisions of gap / error scale (nullable) */
+    int32_t *work;     /* [n][3] probe traces, pieces marched, cells visited (nullable) */
 } out_t;
 
 /* ------------------------------------------------------------------------------------
@@ -451,7 +452,7 @@ typedef struct {
     int texel;
     double t;       /* hit distance along the ray */
     double dirp[3]; /* direction from the probe to the hit point */
-    int tests, normals, flat_tests;
+    int tests, normals, flat_tests, pieces;
 } presult_t;
 
 /* traceOneProbe over [ta, tb] */
@@ -530,6 +531,7 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
     for (int sgi = 0; sgi < nc; ++sgi) {
         piece_t s;
         piece_setup(&s, &r, cut[sgi], cut[sgi + 1], Ecut[sgi], Ecut[sgi + 1], N);
+        res->pieces++;
         fire_t ff = {0}, fh = {0};
         march_flat(g, p, &r, &s, &ff, &res->flat_tests);
         if (o->check_hier) {
@@ -594,7 +596,7 @@ static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const
     mc.bits = 0;
     mc.score = INFINITY;
     mc.delta = o->delta;
-    int tests = 0, normals = 0, flat_tests = 0;
+    int tests = 0, normals = 0, flat_tests = 0, n_probe = 0, n_piece = 0, n_cell = 0;
     /* parameter range: until the ray leaves the scene box (slightly enlarged) */
     double tfar = INFINITY, Efar = 0;
     for (int a = 0; a < 3; ++a) {
@@ -619,6 +621,7 @@ static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const
     int mp = o->max_probes_per_cell < 1 || o->max_probes_per_cell > 8 ? 8 : o->max_probes_per_cell;
     int ordinal = 0;
     while (ta < tfar && tfar > 0) {
+        ++n_cell;
         /* next interior grid plane along each axis */
         double tn[3], En[3];
         for (int a = 0; a < 3; ++a) {
@@ -664,6 +667,8 @@ static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const
                     g->dims[0] * ((cell[1] + ((c >> 1) & 1)) + g->dims[1] * (cell[2] + (c >> 2)));
             presult_t pr;
             trace_one_probe(g, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
+            ++n_probe;
+            n_piece += pr.pieces;
             tests += pr.tests;
             normals += pr.normals;
             flat_tests += pr.flat_tests;
@@ -714,6 +719,11 @@ done:
     out->tests[ri] = tests;
     out->normals[ri] = normals;
     out->flat_tests[ri] = flat_tests;
+    if (out->work) {
+        out->work[3 * ri + 0] = n_probe;
+        out->work[3 * ri + 1] = n_piece;
+        out->work[3 * ri + 2] = n_cell;
+    }
 }
 
 /* ------------------------------------------------------------------------------------

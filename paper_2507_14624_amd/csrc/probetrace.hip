@@ -59,7 +59,7 @@ struct GraphCache {
 struct pt_grid {
     pt_grid_desc desc;
     int device = 0;
-    int P = 0, N = 0, L = 0;
+    int P = 0, N = 0, L = 0, Lc = 0;
     int64_t stride = 0;
     float *pyr = nullptr;
     uint32_t *nrm = nullptr;
@@ -161,6 +161,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     g->N = N;
     g->L = L;
     g->stride = 2 * (int64_t)N * N;
+    g->Lc = 0;
+    while ((2 << g->Lc) <= N) ++g->Lc;  // levels down to 2x2 (log2 N of them)
     g->cells = (desc->dims[0] - 1) * (desc->dims[1] - 1) * (desc->dims[2] - 1);
     hipStream_t s = (hipStream_t)stream;
     auto cleanup = [&](pt_status st, const std::string &m) {
@@ -180,7 +182,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     int64_t total = P * N * N;
     hipLaunchKernelGGL(k_pack, dim3(blocks_for(total, 256)), dim3(256), 0, s, distance_dev, normal_oct_dev, g->pyr,
                        g->nrm, N, g->stride, total);
-    for (int l = 1; l < L; ++l) {
+    for (int l = 1; l < g->Lc; ++l) {
         int64_t tl = P * (int64_t)(N >> l) * (N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, N, l, g->stride, tl);
     }
@@ -447,6 +449,7 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     d.logN = 0;
     while ((1 << d.logN) < g->N) ++d.logN;
     d.L = g->L;
+    d.Lc = g->Lc;
     d.top = (o.start_level < 0 || o.start_level > g->L - 1) ? g->L - 1 : o.start_level;
     d.P = g->P;
     d.stride = g->stride;

@@ -28,8 +28,9 @@ struct GridDev {
     float smin[3], smax[3];
     int N;           // level-0 map resolution (power of two)
     int logN;        // log2(N)
-    int L;           // pyramid levels
+    int L;           // pyramid levels the march may use
     int top;         // level the march starts at
+    int Lc;          // levels held in memory (down to 2x2) for the piece cover test
     int P;           // number of probes
     int64_t stride;  // floats per probe pyramid block
     const float *__restrict__ pyr;     // [P][stride]: level 0, then 1, ... (row-major per level)
@@ -209,11 +210,11 @@ struct Fire {
 
 // Hierarchical march of one piece over the probe's MIN pyramid (block = the probe's
 // pyramid).  Returns true at the first level-0 texel with stored r < max rho.
+// (xs, ys, Ls): texel coordinates and L form of the ray point at s.ts; top: the level the
+// march starts at and never climbs above.
 __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, const float Xp[3], const float w[3],
-                            const Piece &s, Fire &f) {
+                            const Piece &s, float xs, float ys, float Ls, int top, Fire &f) {
     const int N = g.N;
-    float xs, ys, Ls;
-    piece_xy(s, Xp, w, s.ts, N, xs, ys, Ls);
     if (!(Ls > 0.0f)) {  // the piece starts at the probe origin itself
         piece_xy(s, Xp, w, 0.5f * (s.ts + s.te), N, xs, ys, Ls);
         if (!(Ls > 0.0f)) {
@@ -223,7 +224,7 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
     }
     int i0 = min(max((int)floorf(xs), s.ilo), s.ihi);
     int j0 = min(max((int)floorf(ys), s.jlo), s.jhi);
-    int l = g.top;
+    int l = top;
     int I = i0 >> l, J = j0 >> l;
     int off = level_offset(N, l);
     const int last = (int)g.stride - 1;
@@ -274,7 +275,7 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
             int Jn = J + (ty == tmin ? s.dy : 0);
             int diff = (In ^ I) | (Jn ^ J);
             int h = 31 - __builtin_clz((unsigned)diff | 1u);
-            int up = min(h, g.top - l);
+            int up = min(h, top - l);
             I = In >> up;
             J = Jn >> up;
             l += up;
@@ -350,8 +351,38 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         float hi = sgi == nc ? tb : (sgi == 0 ? c0 : (sgi == 1 ? c1 : c2));
         Piece s;
         piece_setup(s, Xp, w, lo, hi, N);
+        float xs, ys, Ls, xe, ye, Le;
+        piece_xy(s, Xp, w, lo, N, xs, ys, Ls);
+        piece_xy(s, Xp, w, hi, N, xe, ye, Le);
+        // O(1) MISS test of the whole piece: its projection is a straight segment, so the
+        // texels it crosses lie in the box spanned by its end texels (widened by one texel
+        // against rounding).  At the pyramid level where that box spans at most 2x2 texels,
+        // if their minimum stored distance is not below the piece's largest radial distance
+        // (at an end: rho is convex) with a 2^-16 slack, no texel can fire.
+        bool miss = false;
+        int top = g.top;
+        if (Ls > 0.0f && Le > 0.0f) {
+            int i0 = min(max((int)floorf(fminf(xs, xe)) - 1, s.ilo), s.ihi);
+            int i1 = min(max((int)floorf(fmaxf(xs, xe)) + 1, s.ilo), s.ihi);
+            int j0 = min(max((int)floorf(fminf(ys, ye)) - 1, s.jlo), s.jhi);
+            int j1 = min(max((int)floorf(fmaxf(ys, ye)) + 1, s.jlo), s.jhi);
+            // smallest level where the box spans at most 2 texels per axis: a difference
+            // below 2^(b+1) spans at most 2 texels at level b or b+1 (b = bit length - 1)
+            int lv = max(31 - __builtin_clz((unsigned)max(max(i1 - i0, j1 - j0), 1)), 0);
+            lv += ((i1 >> lv) - (i0 >> lv) > 1) | ((j1 >> lv) - (j0 >> lv) > 1);
+            lv = min(lv, g.Lc - 1);
+            const float *lev = blk + level_offset(N, lv);
+            int sh = g.logN - lv;
+            int a = i0 >> lv, b = i1 >> lv, c = j0 >> lv, d = j1 >> lv;
+            float mn = fminf(fminf(lev[(c << sh) + a], lev[(c << sh) + b]),
+                             fminf(lev[(d << sh) + a], lev[(d << sh) + b]));
+            float m2 = fmaxf(rho2_at(Xp, w, lo), rho2_at(Xp, w, hi));
+            miss = (mn >= 0.0f) && (mn * mn >= m2 * 1.0000153f);
+            // the whole piece fits 2x2 texels of level lv: no coarser level can skip more
+            top = min(top, lv);
+        }
         Fire f;
-        if (march_piece(g, blk, Xp, w, s, f)) {
+        if (!miss && march_piece(g, blk, Xp, w, s, xs, ys, Ls, top, f)) {
             int k = f.j * N + f.i;
             float r = blk[k];
             res.texel = k;
