@@ -10,7 +10,10 @@ the batched workload (64 views of uneven size in one persistent hipGraph launch)
 64 plain launches, the roofline of the forward kernel and the CPU oracle timed on the
 host.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--autotune]
+
+Launch options (tile shape, pyramid start level, launch form) come from the autotuner's
+stored choice for this workload (paper_2507_14624_amd/tuned.json); --autotune re-tunes.
 """
 import argparse
 import hashlib
@@ -88,7 +91,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="forward only (for profiling)")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the tuned options")
+    ap.add_argument("--autotune", action="store_true", help="re-run the autotuner and store its choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (scales HBM counters)")
     args = ap.parse_args()
@@ -121,9 +125,9 @@ def main():
     rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
     rays = view.width * view.height
     va = pt.make_views([view])
-    opts = pt.trace_opts()
-    if not args.no_autotune:
-        opts = pt.probe_autotune(grid, rad, va, opts)
+    from paper_2507_14624_amd import tuning
+    opts = pt.trace_opts() if args.no_autotune else tuning.options("single_1080p", grid, rad, va,
+                                                                     retune=args.autotune)
     out = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"),
            torch.empty(rays, dtype=torch.uint8, device="cuda"), torch.empty((rays, 2), dtype=torch.int32, device="cuda"))
 

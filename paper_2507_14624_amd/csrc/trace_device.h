@@ -64,6 +64,12 @@ __device__ __forceinline__ float plane_t(float plane, float x, float iw) { retur
 
 __device__ __forceinline__ float sgnp(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
 
+// min / max / clamp of values that are never NaN, as one v_med3_f32 each (fminf/fmaxf
+// would add NaN canonicalisation)
+__device__ __forceinline__ float min_nn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -INFINITY); }
+__device__ __forceinline__ float max_nn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+__device__ __forceinline__ float clamp_nn(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+
 __device__ __forceinline__ float half_bits(uint16_t b) { return __half2float(__ushort_as_half(b)); }
 
 // Octahedral encode (z fold axis), returns (u, v) in [-1, 1]^2.
@@ -137,28 +143,29 @@ __device__ __forceinline__ float rho2_at(const float Xp[3], const float w[3], fl
 struct Piece {
     float A0, A1, B0, B1, L0, L1;
     float ts, te;
-    int dx, dy;
+    int dx, dy;              // motion along x, y: -1, 0, +1
+    float fdx, fdy;          // the same as floats
     int ilo, ihi, jlo, jhi;  // quadrant of the octant (level 0)
 };
 
-__device__ __forceinline__ float cross_t(int c, int dir, float P0, float P1, float L0, float L1) {
+// Crossing of the boundary ahead of texel I (level l) along one axis: c = (I + [d > 0]) 2^l.
+// +inf if the boundary is an edge of the quadrant (never crossed inside a piece) or the ray
+// never reaches it (A1 - c L1 must have the sign of the motion; no motion never reaches).
+__device__ __forceinline__ float cross_axis(int I, int l, int d, float fd, int lo, int hi, float P0, float P1,
+                                            float L0, float L1) {
+    int c = (I + (d > 0)) << l;
     float fc = (float)c;
     float den = __fmaf_rn(-fc, L1, P1);
     float num = __fmaf_rn(fc, L0, -P0);
-    return ((float)dir * den > 0.0f) ? num * frcp(den) : INFINITY;
+    bool ok = (c > lo) & (c <= hi) & (fd * den > 0.0f);
+    return ok ? num * frcp(den) : INFINITY;
 }
 
 __device__ __forceinline__ float next_x(const Piece &s, int I, int l) {
-    if (s.dx == 0) return INFINITY;
-    int c = (s.dx > 0 ? I + 1 : I) << l;
-    if (c <= s.ilo || c > s.ihi) return INFINITY;
-    return cross_t(c, s.dx, s.A0, s.A1, s.L0, s.L1);
+    return cross_axis(I, l, s.dx, s.fdx, s.ilo, s.ihi, s.A0, s.A1, s.L0, s.L1);
 }
 __device__ __forceinline__ float next_y(const Piece &s, int J, int l) {
-    if (s.dy == 0) return INFINITY;
-    int c = (s.dy > 0 ? J + 1 : J) << l;
-    if (c <= s.jlo || c > s.jhi) return INFINITY;
-    return cross_t(c, s.dy, s.B0, s.B1, s.L0, s.L1);
+    return cross_axis(J, l, s.dy, s.fdy, s.jlo, s.jhi, s.B0, s.B1, s.L0, s.L1);
 }
 
 __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const float w[3], float ts, float te,
@@ -182,6 +189,8 @@ __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const f
     float gy = __fmaf_rn(s.B1, s.L0, -(s.B0 * s.L1));
     s.dx = gx > 0.0f ? 1 : (gx < 0.0f ? -1 : 0);
     s.dy = gy > 0.0f ? 1 : (gy < 0.0f ? -1 : 0);
+    s.fdx = (float)s.dx;
+    s.fdy = (float)s.dy;
     s.ts = ts;
     s.te = te;
     s.ilo = sx > 0.0f ? N / 2 : 0;
@@ -233,37 +242,32 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
     float tx = next_x(s, I, l), ty = next_y(s, J, l);
     const int guard = 24 * N + 64;
     for (int it = 0; it < guard; ++it) {
-        // selects, not fminf/fmaxf: the candidates are never NaN and selects need no
-        // NaN canonicalisation
-        float tmin = tx < ty ? tx : ty;
-        float tend = tmin < s.te ? tmin : s.te;
-        float texit = tend > t ? tend : t;
+        float tmin = min_nn(tx, ty);
+        float texit = clamp_nn(tmin, t, s.te);  // t <= te throughout
         float re2 = rho2_at(Xp, w, texit);
-        float m2 = rc2 > re2 ? rc2 : re2;
+        float m2 = max_nn(rc2, re2);
         // the index stays inside the probe block even if the walk were wrong
         float M = blk[min(off + (J << (g.logN - l)) + I, last)];
         // coarse levels test conservatively (the min over a parent must not miss a child
         // whose ray span's rho^2 rounds a little above the parent's endpoints)
         float lim = l == 0 ? m2 : m2 * 1.0000153f;
         bool fire = (M < 0.0f) | (M * M < lim);
-        if (fire && l == 0) {
+        if (fire & (l == 0)) {
             f.i = I;
             f.j = J;
             f.tin = t;
             f.rin2 = rc2;
             return true;
         }
-        if (!fire && !(tmin < s.te)) return false;  // the piece ends inside this texel
+        if (!fire & !(tmin < s.te)) return false;  // the piece ends inside this texel
         if (fire) {
             // descend into the child that holds the ray point at t
-            float x, y, Lt;
-            piece_xy(s, Xp, w, t, N, x, y, Lt);
+            float iL = frcp(__fmaf_rn(t, s.L1, s.L0));
+            float x = __fmaf_rn(t, s.A1, s.A0) * iL;
+            float y = __fmaf_rn(t, s.B1, s.B0) * iL;
             --l;
-            off = level_offset(N, l);
-            float sc = __builtin_ldexpf(1.0f, -l);
-            int ci = (int)floorf(x * sc), cj = (int)floorf(y * sc);
-            ci = min(max(ci, 2 * I), 2 * I + 1);
-            cj = min(max(cj, 2 * J), 2 * J + 1);
+            int ci = min(max((int)floorf(x) >> l, 2 * I), 2 * I + 1);
+            int cj = min(max((int)floorf(y) >> l, 2 * J), 2 * J + 1);
             I = min(max(ci, s.ilo >> l), s.ihi >> l);
             J = min(max(cj, s.jlo >> l), s.jhi >> l);
         } else {
@@ -279,10 +283,10 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
             I = In >> up;
             J = Jn >> up;
             l += up;
-            off = level_offset(N, l);
             t = texit;
             rc2 = re2;
         }
+        off = level_offset(N, l);
         tx = next_x(s, I, l);
         ty = next_y(s, J, l);
     }
