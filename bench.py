@@ -84,6 +84,48 @@ def cpu_baseline(probes, view):
                        f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()))
 
 
+def differentiable(pt, synth, torch, np, steps=5):
+    """16x16x8 probes, 256^2 maps, 32 views of 512^2: Adam on FP32 master radiance against
+    images of a second radiance field (same geometry, albedos redrawn)."""
+    from paper_2507_14624_amd.differentiable import RadianceFit
+    scene, probes, views = synth.workload("diff")
+    target_probes = synth.bake(scene.with_albedos(synth.CONFIGS["diff"]["target_seed"]), probes.N, probes.levels)
+    grid = pt.ProbeGrid.from_probes(probes)
+    trad = torch.from_numpy(target_probes.radiance.view(np.float16).copy()).cuda()
+    del target_probes
+    target = pt.probe_trace(grid, trad, views, want_t=False, want_status=False, want_hit=False)["rgb"]
+    del trad
+    rays = pt.n_rays(views)
+    fit = RadianceFit(grid, views, target)
+    losses = [fit.step().item()]  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = [fit.step() for _ in range(steps)]
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    losses += [x.item() for x in out]
+    # the trace kernels alone in one step: forward and backward
+    va = pt.make_views(views)
+    g = torch.zeros((grid.P, grid.N, grid.N, 3), device="cuda")
+    storage = fit.master.detach().to(torch.float16)
+    gr = torch.randn((rays, 3), device="cuda")
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, storage, va, want_t=False, want_status=False, want_hit=False)
+        pt.probe_trace_backward(grid, va, gr, g)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / steps
+    return {"workload": "16x16x8 probes, 256^2 maps (6 levels), 32 views of 512x512; FP32 master, FP16 storage; "
+                        "Adam lr 1e-2 from 0.5",
+            "rays_per_step": rays, "adam_step_ms": round(ms, 3),
+            "adam_step_mrays_s": round(rays / (ms * 1e-3) / 1e6, 2),
+            "fwd_bwd_kernels_ms": round(ms_fb, 3), "fwd_bwd_mrays_s": round(rays / (ms_fb * 1e-3) / 1e6, 2),
+            "loss": [round(x, 6) for x in losses]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +133,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="forward only (for profiling)")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable workload")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the tuned options")
     ap.add_argument("--autotune", action="store_true", help="re-run the autotuner and store its choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -202,6 +245,9 @@ def main():
                                                   "ms": round(ms_g, 3)},
                              "plain_launches": {"value": round(brays / (ms_p * 1e-3) / 1e6, 3), "unit": "Mrays/s",
                                                 "ms": round(ms_p, 3)}}
+    if not args.no_extras and not args.no_diff:
+        print("[bench] differentiable workload", file=sys.stderr, flush=True)
+        result["differentiable"] = differentiable(pt, synth, torch, np)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(probes, view)

@@ -248,7 +248,7 @@ def trace_view(grid: Grid, view, pixels=None, **kw) -> dict:
 
 
 def vjp(grid: Grid, result: dict, grad_rgb: np.ndarray) -> np.ndarray:
-    """Adjoint of the radiance fetch with the hit test held fixed (spec extension):
+    """Adjoint of the radiance fetch with the hit test held fixed (an extension beyond the paper, which renders forward only):
     dL/dRad[p][tap][c] = sum over HIT rays of w_tap * dL/drgb[c].  Accumulated in double,
     duplicate taps add up."""
     P = grid.distance.shape[0]

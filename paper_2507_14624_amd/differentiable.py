@@ -1,0 +1,38 @@
+"""Fitting probe radiance to images through the probe trace.
+
+The trace is linear in the stored radiance once the hit test is fixed, so an image loss
+can be minimised over the radiance texels with its exact gradient (ProbeTraceFn ->
+probe_trace_backward).  The master radiance is FP32 and is rounded to the FP16 storage
+the trace reads on every forward; Adam (torch) updates the master.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ProbeTraceFn, make_views
+
+
+class RadianceFit:
+    """Adam on FP32 master radiance [P,N,N,3] against target images of the given views."""
+
+    def __init__(self, grid, views, target_rgb, init=0.5, lr=1e-2, opts=None):
+        self.grid = grid
+        self.views = make_views(views)
+        self.target = target_rgb
+        shape = (grid.P, grid.N, grid.N, 3)
+        self.master = torch.full(shape, float(init), dtype=torch.float32, device=target_rgb.device,
+                                 requires_grad=True)
+        self.optim = torch.optim.Adam([self.master], lr=lr)
+        self.opts = opts
+
+    def loss(self):
+        rgb = ProbeTraceFn.apply(self.master, self.grid, self.views, self.opts)
+        return ((rgb - self.target) ** 2).mean()
+
+    def step(self) -> torch.Tensor:
+        """One Adam step; returns the loss before the update (device scalar)."""
+        self.optim.zero_grad(set_to_none=False)
+        loss = self.loss()
+        loss.backward()
+        self.optim.step()
+        return loss.detach()

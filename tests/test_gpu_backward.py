@@ -145,14 +145,10 @@ def test_adam_reduces_loss_on_small_differentiable_room():
     trad = torch.from_numpy(target_probes.radiance.view(np.float16).copy()).cuda()
     with torch.no_grad():
         target = pt.probe_trace(grid, trad, views)["rgb"]
-    master = torch.full((probes.n_probes, probes.N, probes.N, 3), 0.5, device="cuda", requires_grad=True)
-    optim = torch.optim.Adam([master], lr=1e-2)
-    losses = []
-    for step in range(30):
-        optim.zero_grad()
-        rgb = pt.ProbeTraceFn.apply(master, grid, views)
-        loss = ((rgb - target) ** 2).mean()
-        loss.backward()
-        optim.step()
-        losses.append(loss.item())
+    from paper_2507_14624_amd.differentiable import RadianceFit
+    fit = RadianceFit(grid, views, target, init=0.5, lr=1e-2)
+    losses = [fit.step().item() for _ in range(30)]
     assert losses[-1] < 0.5 * losses[0], losses
+    # the helper's loss is the mean squared error of the traced FP16-rounded master
+    rgb = pt.probe_trace(grid, fit.master.detach().to(torch.float16), views)["rgb"]
+    torch.testing.assert_close(fit.loss().detach(), ((rgb - target) ** 2).mean(), rtol=1e-6, atol=0)
