@@ -154,6 +154,9 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: mip_levels must satisfy N >> (L-1) >= 2");
     int64_t P = (int64_t)desc->dims[0] * desc->dims[1] * desc->dims[2];
     if (P > (1 << 24)) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: too many probes");
+    // the trace addresses the pyramid (2 N^2 floats per probe) with 32-bit byte offsets
+    if (P * 2 * (int64_t)N * N * (int64_t)sizeof(float) > (int64_t)UINT32_MAX)
+        return fail(PT_ERR_UNSUPPORTED, "probe_grid_create: probes x 8 N^2 bytes must stay below 4 GiB");
     pt_grid *g = new (std::nothrow) pt_grid();
     if (!g) return fail(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: host allocation");
     g->desc = *desc;
@@ -453,6 +456,8 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     d.top = (o.start_level < 0 || o.start_level > g->L - 1) ? g->L - 1 : o.start_level;
     d.P = g->P;
     d.stride = g->stride;
+    d.stride32 = (uint32_t)g->stride;
+    d.inf = INFINITY;
     d.pyr = g->pyr;
     d.nrm = g->nrm;
     float tau = o.thickness_rel > 0.0f ? o.thickness_rel : 8.0f / (float)g->N;

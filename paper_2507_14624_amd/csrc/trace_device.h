@@ -33,12 +33,15 @@ struct GridDev {
     int Lc;          // levels held in memory (down to 2x2) for the piece cover test
     int P;           // number of probes
     int64_t stride;  // floats per probe pyramid block
+    uint32_t stride32;  // the same; the whole pyramid is below 4 GiB, so probe blocks and
+                        // texels are addressed by 32-bit byte offsets from pyr
     const float *__restrict__ pyr;     // [P][stride]: level 0, then 1, ... (row-major per level)
     const uint32_t *__restrict__ nrm;  // [P][N*N] packed FP16 (u, v) of the stored normal
     float eye_eps2;  // (eye_eps_rel * min spacing)^2
     float tau1;      // 1 + thickness
     float bg[3];
     int max_probes;
+    float inf;       // +INFINITY, set by the host (see min_nn)
 };
 
 // Offset of level l inside a probe block: 2 (N^2 - (N>>l)^2).  The gap between levels l and
@@ -48,6 +51,16 @@ __host__ __device__ __forceinline__ int level_offset(int N, int l) {
     int NN = N * N;
     return 2 * (NN - (NN >> (2 * l)));
 }
+
+// Texel `idx` (floats from the start of the pyramid); the byte offset fits 32 bits, so the
+// load takes the pyramid base from scalar registers plus one 32-bit lane offset.
+__device__ __forceinline__ float pyr_at(const GridDev &g, uint32_t idx) {
+    return *(const float *)((const char *)g.pyr + (idx << 2));
+}
+
+// fire test of a stored distance M against a squared radial distance: M^2 < lim for
+// M >= 0, always for M < 0 (one product: M |M| is negative exactly when M is)
+__device__ __forceinline__ bool below(float M, float lim) { return M * fabsf(M) < lim; }
 
 // grid plane / probe coordinate along axis a (shared by the cell iterator and the probes)
 __device__ __forceinline__ float grid_coord(const GridDev &g, int a, int idx) {
@@ -64,11 +77,19 @@ __device__ __forceinline__ float plane_t(float plane, float x, float iw) { retur
 
 __device__ __forceinline__ float sgnp(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
 
-// min / max / clamp of values that are never NaN, as one v_med3_f32 each (fminf/fmaxf
-// would add NaN canonicalisation)
-__device__ __forceinline__ float min_nn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -INFINITY); }
-__device__ __forceinline__ float max_nn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+// min / max / clamp of values that are never NaN, as one v_med3_f32 each.  fminf/fmaxf
+// (and a median with a literal infinity, which the compiler rewrites into them) add NaN
+// canonicalisation of both inputs; the infinity here is the grid's `inf` field, a kernel
+// argument the compiler cannot see through.
+__device__ __forceinline__ float min_nn(float inf, float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -inf); }
+__device__ __forceinline__ float max_nn(float inf, float a, float b) { return __builtin_amdgcn_fmed3f(a, b, inf); }
 __device__ __forceinline__ float clamp_nn(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+
+// max of two floats that are both >= +0 (squared lengths): their bit patterns order like
+// the values, so one integer max
+__device__ __forceinline__ float max_pos(float a, float b) {
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
 
 __device__ __forceinline__ float half_bits(uint16_t b) { return __half2float(__ushort_as_half(b)); }
 
@@ -217,66 +238,53 @@ struct Fire {
     float rin2;     // rho^2 at entry
 };
 
-// Hierarchical march of one piece over the probe's MIN pyramid (block = the probe's
-// pyramid).  Returns true at the first level-0 texel with stored r < max rho.
-// (xs, ys, Ls): texel coordinates and L form of the ray point at s.ts; top: the level the
-// march starts at and never climbs above.
-__device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, const float Xp[3], const float w[3],
-                            const Piece &s, float xs, float ys, float Ls, int top, Fire &f) {
+// Hierarchical march of one piece over the probe's MIN pyramid (base = first float of the
+// probe's pyramid block).  Returns true at the first level-0 texel with stored r < max rho.
+// (i0, j0): level-0 texel of the ray point at s.ts; rc2: rho^2 there; top: the level the
+// march starts at and never climbs above (at most log2 N - 1, where each quadrant is one
+// texel, so the two children of a texel inside the piece's quadrant are inside it too).
+__device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], const float w[3], const Piece &s,
+                            int i0, int j0, float rc2, int top, Fire &f) {
     const int N = g.N;
-    if (!(Ls > 0.0f)) {  // the piece starts at the probe origin itself
-        piece_xy(s, Xp, w, 0.5f * (s.ts + s.te), N, xs, ys, Ls);
-        if (!(Ls > 0.0f)) {
-            xs = (float)s.ilo;
-            ys = (float)s.jlo;
-        }
-    }
-    int i0 = min(max((int)floorf(xs), s.ilo), s.ihi);
-    int j0 = min(max((int)floorf(ys), s.jlo), s.jhi);
     int l = top;
     int I = i0 >> l, J = j0 >> l;
-    int off = level_offset(N, l);
-    const int last = (int)g.stride - 1;
+    uint32_t off = base + (uint32_t)level_offset(N, l);
+    const uint32_t last = base + g.stride32 - 1u;
     float t = s.ts;
-    float rc2 = rho2_at(Xp, w, t);
     float tx = next_x(s, I, l), ty = next_y(s, J, l);
     const int guard = 24 * N + 64;
+    bool found = false;
+    // one exit: the loop state at the exit is the answer (the compiler then keeps the
+    // state in place instead of copying candidate outputs around the loop)
     for (int it = 0; it < guard; ++it) {
-        float tmin = min_nn(tx, ty);
+        bool ax = tx <= ty, ay = ty <= tx;  // the axis (or both) whose boundary comes first
+        float tmin = ax ? tx : ty;
         float texit = clamp_nn(tmin, t, s.te);  // t <= te throughout
         float re2 = rho2_at(Xp, w, texit);
-        float m2 = max_nn(rc2, re2);
+        float m2 = max_pos(rc2, re2);
         // the index stays inside the probe block even if the walk were wrong
-        float M = blk[min(off + (J << (g.logN - l)) + I, last)];
+        float M = pyr_at(g, min(off + ((uint32_t)J << (g.logN - l)) + (uint32_t)I, last));
         // coarse levels test conservatively (the min over a parent must not miss a child
         // whose ray span's rho^2 rounds a little above the parent's endpoints)
         float lim = l == 0 ? m2 : m2 * 1.0000153f;
-        bool fire = (M < 0.0f) | (M * M < lim);
-        if (fire & (l == 0)) {
-            f.i = I;
-            f.j = J;
-            f.tin = t;
-            f.rin2 = rc2;
-            return true;
-        }
-        if (!fire & !(tmin < s.te)) return false;  // the piece ends inside this texel
+        bool fire = below(M, lim);
+        found = fire & (l == 0);
+        if (found | (!fire & !(tmin < s.te))) break;  // level-0 fire, or the piece ends in this texel
         if (fire) {
             // descend into the child that holds the ray point at t
             float iL = frcp(__fmaf_rn(t, s.L1, s.L0));
             float x = __fmaf_rn(t, s.A1, s.A0) * iL;
             float y = __fmaf_rn(t, s.B1, s.B0) * iL;
             --l;
-            int ci = min(max((int)floorf(x) >> l, 2 * I), 2 * I + 1);
-            int cj = min(max((int)floorf(y) >> l, 2 * J), 2 * J + 1);
-            I = min(max(ci, s.ilo >> l), s.ihi >> l);
-            J = min(max(cj, s.jlo >> l), s.jhi >> l);
+            I = min(max((int)floorf(x) >> l, 2 * I), 2 * I + 1);
+            J = min(max((int)floorf(y) >> l, 2 * J), 2 * J + 1);
         } else {
             // step past the texel; a finite candidate implies the crossed boundary lies
             // inside the quadrant, so the stepped index stays in range.  Move up while the
             // step left the parent: the parents differ at every shift up to the highest
             // bit in which the old and new indices differ.
-            int In = I + (tx == tmin ? s.dx : 0);
-            int Jn = J + (ty == tmin ? s.dy : 0);
+            int In = I + (ax ? s.dx : 0);
+            int Jn = J + (ay ? s.dy : 0);
             int diff = (In ^ I) | (Jn ^ J);
             int h = 31 - __builtin_clz((unsigned)diff | 1u);
             int up = min(h, top - l);
@@ -286,11 +294,15 @@ __device__ bool march_piece(const GridDev &g, const float *__restrict__ blk, con
             t = texit;
             rc2 = re2;
         }
-        off = level_offset(N, l);
+        off = base + (uint32_t)level_offset(N, l);
         tx = next_x(s, I, l);
         ty = next_y(s, J, l);
     }
-    return false;
+    f.i = I;
+    f.j = J;
+    f.tin = t;
+    f.rin2 = rc2;
+    return found;
 }
 
 struct ProbeResult {
@@ -309,7 +321,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
     float Xp[3] = {X[0] - O[0], X[1] - O[1], X[2] - O[2]};
     res.status = ST_MISS;
     res.texel = -1;
-    const float *blk = g.pyr + (int64_t)p * g.stride;
+    const uint32_t base = (uint32_t)p * g.stride32;
     float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
     if (d2 <= g.eye_eps2) {
         // eye aligned with the probe: every ray point maps to oct(w)
@@ -317,7 +329,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         oct_encode(w[0], w[1], w[2], u, v);
         int i = min(max((int)floorf(__fmaf_rn(u + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
         int j = min(max((int)floorf(__fmaf_rn(v + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
-        float r = blk[j * N + i];
+        float r = pyr_at(g, base + (uint32_t)(j * N + i));
         if (r >= ta && r <= tb) {
             res.status = ST_HIT;
             res.texel = j * N + i;
@@ -358,37 +370,58 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         float xs, ys, Ls, xe, ye, Le;
         piece_xy(s, Xp, w, lo, N, xs, ys, Ls);
         piece_xy(s, Xp, w, hi, N, xe, ye, Le);
-        // O(1) MISS test of the whole piece: its projection is a straight segment, so the
-        // texels it crosses lie in the box spanned by its end texels (widened by one texel
-        // against rounding).  At the pyramid level where that box spans at most 2x2 texels,
-        // if their minimum stored distance is not below the piece's largest radial distance
-        // (at an end: rho is convex) with a 2^-16 slack, no texel can fire.
+        float rs2 = rho2_at(Xp, w, lo);
         bool miss = false;
         int top = g.top;
+        int i0, j0;  // level-0 texel where the march starts
         if (Ls > 0.0f && Le > 0.0f) {
-            int i0 = min(max((int)floorf(fminf(xs, xe)) - 1, s.ilo), s.ihi);
-            int i1 = min(max((int)floorf(fmaxf(xs, xe)) + 1, s.ilo), s.ihi);
-            int j0 = min(max((int)floorf(fminf(ys, ye)) - 1, s.jlo), s.jhi);
-            int j1 = min(max((int)floorf(fmaxf(ys, ye)) + 1, s.jlo), s.jhi);
+            int fxs = (int)floorf(xs), fys = (int)floorf(ys);
+            int fxe = (int)floorf(xe), fye = (int)floorf(ye);
+            i0 = min(max(fxs, s.ilo), s.ihi);
+            j0 = min(max(fys, s.jlo), s.jhi);
+            // O(1) MISS test of the whole piece: its projection is a straight segment, so the
+            // texels it crosses lie in the box spanned by its end texels (widened by one texel
+            // against rounding).  At the pyramid level where that box spans at most 2x2
+            // texels, if their minimum stored distance is not below the piece's largest radial
+            // distance (at an end: rho is convex) with a 2^-16 slack, no texel can fire.
+            int bi0 = min(max(min(fxs, fxe) - 1, s.ilo), s.ihi);
+            int bi1 = min(max(max(fxs, fxe) + 1, s.ilo), s.ihi);
+            int bj0 = min(max(min(fys, fye) - 1, s.jlo), s.jhi);
+            int bj1 = min(max(max(fys, fye) + 1, s.jlo), s.jhi);
             // smallest level where the box spans at most 2 texels per axis: a difference
             // below 2^(b+1) spans at most 2 texels at level b or b+1 (b = bit length - 1)
-            int lv = max(31 - __builtin_clz((unsigned)max(max(i1 - i0, j1 - j0), 1)), 0);
-            lv += ((i1 >> lv) - (i0 >> lv) > 1) | ((j1 >> lv) - (j0 >> lv) > 1);
+            int lv = 31 - __builtin_clz((unsigned)max(max(bi1 - bi0, bj1 - bj0), 1));
+            lv += ((bi1 >> lv) - (bi0 >> lv) > 1) | ((bj1 >> lv) - (bj0 >> lv) > 1);
             lv = min(lv, g.Lc - 1);
-            const float *lev = blk + level_offset(N, lv);
+            uint32_t lev = base + (uint32_t)level_offset(N, lv);
             int sh = g.logN - lv;
-            int a = i0 >> lv, b = i1 >> lv, c = j0 >> lv, d = j1 >> lv;
-            float mn = fminf(fminf(lev[(c << sh) + a], lev[(c << sh) + b]),
-                             fminf(lev[(d << sh) + a], lev[(d << sh) + b]));
-            float m2 = fmaxf(rho2_at(Xp, w, lo), rho2_at(Xp, w, hi));
-            miss = (mn >= 0.0f) && (mn * mn >= m2 * 1.0000153f);
+            uint32_t a = (uint32_t)(bi0 >> lv), b = (uint32_t)(bi1 >> lv);
+            uint32_t c = (uint32_t)(bj0 >> lv) << sh, d = (uint32_t)(bj1 >> lv) << sh;
+            float lim = max_pos(rs2, rho2_at(Xp, w, hi)) * 1.0000153f;
+            // each texel tested on its own: a texel without data (NaN) never fires
+            miss = !(below(pyr_at(g, lev + c + a), lim) | below(pyr_at(g, lev + c + b), lim) |
+                     below(pyr_at(g, lev + d + a), lim) | below(pyr_at(g, lev + d + b), lim));
             // the whole piece fits 2x2 texels of level lv: no coarser level can skip more
             top = min(top, lv);
+        } else {
+            // an end of the piece is the probe origin: start from the texel of the start
+            // point, or of the midpoint if the start is the origin
+            float xm = xs, ym = ys;
+            if (!(Ls > 0.0f)) {
+                float Lm;
+                piece_xy(s, Xp, w, 0.5f * (s.ts + s.te), N, xm, ym, Lm);
+                if (!(Lm > 0.0f)) {
+                    xm = (float)s.ilo;
+                    ym = (float)s.jlo;
+                }
+            }
+            i0 = min(max((int)floorf(xm), s.ilo), s.ihi);
+            j0 = min(max((int)floorf(ym), s.jlo), s.jhi);
         }
         Fire f;
-        if (!miss && march_piece(g, blk, Xp, w, s, xs, ys, Ls, top, f)) {
+        if (!miss && march_piece(g, base, Xp, w, s, i0, j0, rs2, top, f)) {
             int k = f.j * N + f.i;
-            float r = blk[k];
+            float r = pyr_at(g, base + (uint32_t)k);
             res.texel = k;
             float thr = r * g.tau1;
             // shadow entry: the ray entered the texel behind the stored surface
@@ -397,7 +430,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
                 res.status = ST_UNKNOWN;
                 return;
             }
-            uint32_t nb = g.nrm[(int64_t)p * N * N + k];
+            uint32_t nb = *(const uint32_t *)((const char *)g.nrm + (((uint32_t)p * (uint32_t)(N * N) + (uint32_t)k) << 2));
             float nx, ny, nz;
             oct_decode_unnorm(half_bits((uint16_t)(nb & 0xffffu)), half_bits((uint16_t)(nb >> 16)), nx, ny, nz);
             float nd = __fmaf_rn(nz, w[2], __fmaf_rn(ny, w[1], nx * w[0]));
