@@ -165,28 +165,34 @@ struct Piece {
     float A0, A1, B0, B1, L0, L1;
     float ts, te;
     int dx, dy;              // motion along x, y: -1, 0, +1
-    float fdx, fdy;          // the same as floats
     int ilo, ihi, jlo, jhi;  // quadrant of the octant (level 0)
+    // Crossing forms pre-multiplied by the motion sign d (exact: d = +-1 or 0), so that
+    // t = (c Lx - Ax) / (Px - c Lx1) needs no sign test beyond "denominator > 0":
+    //   nAx = -d A0, Lx = d L0, Px = d A1, Lx1 = d L1 (and likewise for y with B).
+    float nAx, Lx, Px, Lx1, nBy, Ly, Py, Ly1;
+    int ex, ey;              // quadrant edge ahead of the motion (level-0 units)
 };
 
 // Crossing of the boundary ahead of texel I (level l) along one axis: c = (I + [d > 0]) 2^l.
-// +inf if the boundary is an edge of the quadrant (never crossed inside a piece) or the ray
-// never reaches it (A1 - c L1 must have the sign of the motion; no motion never reaches).
-__device__ __forceinline__ float cross_axis(int I, int l, int d, float fd, int lo, int hi, float P0, float P1,
-                                            float L0, float L1) {
-    int c = (I + (d > 0)) << l;
+// +inf if that boundary is the quadrant's edge in the direction of motion (texels never
+// leave the quadrant, so c only reaches the edge, never passes it) or the ray never reaches
+// it (the signed denominator is not positive; no motion never reaches).  Equal bit for bit
+// to (c L0 - A0) * rcp(A1 - c L1): the sign d cancels exactly.
+__device__ __forceinline__ float cross_axis(int I, int l, int inc, int edge, float nA, float Lf, float Pf,
+                                            float L1f) {
+    int c = (I + inc) << l;
     float fc = (float)c;
-    float den = __fmaf_rn(-fc, L1, P1);
-    float num = __fmaf_rn(fc, L0, -P0);
-    bool ok = (c > lo) & (c <= hi) & (fd * den > 0.0f);
+    float den = __fmaf_rn(-fc, L1f, Pf);
+    float num = __fmaf_rn(fc, Lf, nA);
+    bool ok = (c != edge) & (den > 0.0f);
     return ok ? num * frcp(den) : INFINITY;
 }
 
 __device__ __forceinline__ float next_x(const Piece &s, int I, int l) {
-    return cross_axis(I, l, s.dx, s.fdx, s.ilo, s.ihi, s.A0, s.A1, s.L0, s.L1);
+    return cross_axis(I, l, s.dx > 0, s.ex, s.nAx, s.Lx, s.Px, s.Lx1);
 }
 __device__ __forceinline__ float next_y(const Piece &s, int J, int l) {
-    return cross_axis(J, l, s.dy, s.fdy, s.jlo, s.jhi, s.B0, s.B1, s.L0, s.L1);
+    return cross_axis(J, l, s.dy > 0, s.ey, s.nBy, s.Ly, s.Py, s.Ly1);
 }
 
 __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const float w[3], float ts, float te,
@@ -210,14 +216,23 @@ __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const f
     float gy = __fmaf_rn(s.B1, s.L0, -(s.B0 * s.L1));
     s.dx = gx > 0.0f ? 1 : (gx < 0.0f ? -1 : 0);
     s.dy = gy > 0.0f ? 1 : (gy < 0.0f ? -1 : 0);
-    s.fdx = (float)s.dx;
-    s.fdy = (float)s.dy;
+    float fdx = (float)s.dx, fdy = (float)s.dy;
+    s.nAx = -(fdx * s.A0);
+    s.Lx = fdx * s.L0;
+    s.Px = fdx * s.A1;
+    s.Lx1 = fdx * s.L1;
+    s.nBy = -(fdy * s.B0);
+    s.Ly = fdy * s.L0;
+    s.Py = fdy * s.B1;
+    s.Ly1 = fdy * s.L1;
     s.ts = ts;
     s.te = te;
     s.ilo = sx > 0.0f ? N / 2 : 0;
     s.ihi = sx > 0.0f ? N - 1 : N / 2 - 1;
     s.jlo = sy > 0.0f ? N / 2 : 0;
     s.jhi = sy > 0.0f ? N - 1 : N / 2 - 1;
+    s.ex = s.dx > 0 ? s.ihi + 1 : s.ilo;
+    s.ey = s.dy > 0 ? s.jhi + 1 : s.jlo;
 }
 
 // Texel-unit coordinates of the ray point at t, evaluated from the point itself.
@@ -308,8 +323,11 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
 struct ProbeResult {
     int status;
     int texel;     // j*N + i
-    float t;       // hit distance
-    float q[3];    // hit point relative to the probe
+    // HIT only: what the hit distance is computed from once the ray is done
+    float tin;     // entry parameter of the firing texel
+    float rin2;    // rho^2 there
+    float r;       // stored distance of the texel
+    bool eye;      // eye aligned with the probe: t = r, the hit direction is w
 };
 
 // traceOneProbe over [ta, tb] for probe (pi, pj, pk).
@@ -321,6 +339,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
     float Xp[3] = {X[0] - O[0], X[1] - O[1], X[2] - O[2]};
     res.status = ST_MISS;
     res.texel = -1;
+    res.eye = false;
     const uint32_t base = (uint32_t)p * g.stride32;
     float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
     if (d2 <= g.eye_eps2) {
@@ -333,34 +352,23 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         if (r >= ta && r <= tb) {
             res.status = ST_HIT;
             res.texel = j * N + i;
-            res.t = r;
-            res.q[0] = w[0];
-            res.q[1] = w[1];
-            res.q[2] = w[2];
+            res.r = r;
+            res.eye = true;
         }
         return;
     }
-    // split [ta, tb] where a coordinate of X - O + t w changes sign (at most 3 cuts)
-    float c0 = INFINITY, c1 = INFINITY, c2 = INFINITY;
+    // split [ta, tb] where a coordinate of X - O + t w changes sign: at most 3 cuts, sorted
+    // by a min / median / max network (a cut outside (ta, tb) or on a still axis is +inf)
+    float cut[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (w[a] != 0.0f) {
-            float tz = plane_t(O[a], X[a], iw[a]);
-            if (tz > ta && tz < tb) {
-                // insert into the sorted triple
-                if (tz < c0) {
-                    c2 = c1;
-                    c1 = c0;
-                    c0 = tz;
-                } else if (tz < c1) {
-                    c2 = c1;
-                    c1 = tz;
-                } else {
-                    c2 = tz;
-                }
-            }
-        }
+        float tz = plane_t(O[a], X[a], iw[a]);
+        cut[a] = ((w[a] != 0.0f) & (tz > ta) & (tz < tb)) ? tz : INFINITY;
     }
+    float lo01 = min_nn(g.inf, cut[0], cut[1]), hi01 = max_nn(g.inf, cut[0], cut[1]);
+    float c0 = min_nn(g.inf, lo01, cut[2]);
+    float c1 = clamp_nn(cut[2], lo01, hi01);
+    float c2 = max_nn(g.inf, hi01, cut[2]);
     int nc = (c0 < INFINITY) + (c1 < INFINITY) + (c2 < INFINITY);
     float lo = ta;
     for (int sgi = 0; sgi <= nc; ++sgi) {
@@ -439,25 +447,9 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
                 return;
             }
             res.status = ST_HIT;
-            float th;
-            if (f.rin2 >= r * r) {
-                th = f.tin;
-            } else {
-                // larger root of |Xp + t w| = r, cancellation-free
-                float b = __fmaf_rn(Xp[2], w[2], __fmaf_rn(Xp[1], w[1], Xp[0] * w[0]));
-                float px = __fmaf_rn(-b, w[0], Xp[0]);
-                float py = __fmaf_rn(-b, w[1], Xp[1]);
-                float pz = __fmaf_rn(-b, w[2], Xp[2]);
-                float dp = sqrtf(__fmaf_rn(pz, pz, __fmaf_rn(py, py, px * px)));
-                float disc = fmaxf((r - dp) * (r + dp), 0.0f);
-                float sq = sqrtf(disc);
-                float dist = sqrtf(d2);
-                th = b <= 0.0f ? sq - b : ((r - dist) * (r + dist)) / (b + sq);
-            }
-            res.t = th;
-            res.q[0] = __fmaf_rn(th, w[0], Xp[0]);
-            res.q[1] = __fmaf_rn(th, w[1], Xp[1]);
-            res.q[2] = __fmaf_rn(th, w[2], Xp[2]);
+            res.tin = f.tin;
+            res.rin2 = f.rin2;
+            res.r = r;
             return;
         }
         lo = hi;
@@ -536,7 +528,9 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
         float q = (X[a] - g.org[a]) * g.ispc[a];
         cell[a] = min(max((int)floorf(q), 0), g.n[a] - 2);
     }
-    bool any_unknown = false;
+    bool any_unknown = false, hit = false;
+    ProbeResult hp;
+    int hc[3] = {0, 0, 0};  // grid coordinates of the HIT probe
     float ta = 0.0f;
     const int max_cells = g.n[0] + g.n[1] + g.n[2];
     for (int ci = 0; ci < max_cells; ++ci) {
@@ -554,26 +548,65 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
             int c = (int)(order & 7u);
             order >>= 3;
             ProbeResult pr;
-            trace_probe(g, cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2), X, w, iw, ta, tb, pr);
+            int pc[3] = {cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2)};
+            trace_probe(g, pc[0], pc[1], pc[2], X, w, iw, ta, tb, pr);
             if (pr.status == ST_HIT) {
-                out.status = ST_HIT;
-                out.probe = (cell[0] + (c & 1)) + g.n[0] * ((cell[1] + ((c >> 1) & 1)) + g.n[1] * (cell[2] + (c >> 2)));
-                out.texel = pr.texel;
-                out.t = pr.t;
-                out.q[0] = pr.q[0];
-                out.q[1] = pr.q[1];
-                out.q[2] = pr.q[2];
-                return;
+                hit = true;
+                hp = pr;
+                hc[0] = pc[0];
+                hc[1] = pc[1];
+                hc[2] = pc[2];
+                break;
             }
             if (pr.status == ST_UNKNOWN) any_unknown = true;
         }
-        if (!(tb < tfar)) break;
+        if (hit || !(tb < tfar)) break;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             if (tn[a] == tb) cell[a] += w[a] > 0.0f ? 1 : -1;
         ta = tb;
     }
-    out.status = any_unknown ? ST_UNKNOWN : ST_MISS;
+    if (!hit) {
+        out.status = any_unknown ? ST_UNKNOWN : ST_MISS;
+        return;
+    }
+    // Hit distance and point, once per ray after the walk (the lanes of a wavefront reach
+    // their HIT at different steps; computing it here keeps the square roots out of the
+    // divergent walk).
+    out.status = ST_HIT;
+    out.probe = hc[0] + g.n[0] * (hc[1] + g.n[1] * hc[2]);
+    out.texel = hp.texel;
+    if (hp.eye) {
+        out.t = hp.r;
+        out.q[0] = w[0];
+        out.q[1] = w[1];
+        out.q[2] = w[2];
+        return;
+    }
+    float Xp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord(g, a, hc[a]);
+    const float r = hp.r;
+    float th;
+    if (hp.rin2 >= r * r) {
+        th = hp.tin;  // entered the texel beyond the stored distance: the hit is the entry
+    } else {
+        // larger root of |Xp + t w| = r, cancellation-free
+        float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
+        float b = __fmaf_rn(Xp[2], w[2], __fmaf_rn(Xp[1], w[1], Xp[0] * w[0]));
+        float px = __fmaf_rn(-b, w[0], Xp[0]);
+        float py = __fmaf_rn(-b, w[1], Xp[1]);
+        float pz = __fmaf_rn(-b, w[2], Xp[2]);
+        float dp = sqrtf(__fmaf_rn(pz, pz, __fmaf_rn(py, py, px * px)));
+        float disc = fmaxf((r - dp) * (r + dp), 0.0f);
+        float sq = sqrtf(disc);
+        float dist = sqrtf(d2);
+        th = b <= 0.0f ? sq - b : ((r - dist) * (r + dist)) / (b + sq);
+    }
+    out.t = th;
+    out.q[0] = __fmaf_rn(th, w[0], Xp[0]);
+    out.q[1] = __fmaf_rn(th, w[1], Xp[1]);
+    out.q[2] = __fmaf_rn(th, w[2], Xp[2]);
 }
 
 // Pinhole ray of pixel (x, y).
