@@ -95,16 +95,16 @@ __global__ void k_pack(const float *__restrict__ dist, const uint16_t *__restric
 __global__ void k_mip(float *__restrict__ pyr, int N, int l, int64_t stride, int64_t total) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
-    int nl = N >> l, nc = N >> (l - 1);
+    int nl = N >> l;
     int64_t per = (int64_t)nl * nl;
     int64_t p = g / per;
     int k = (int)(g % per);
     int i = k % nl, j = k / nl;
     float *blk = pyr + p * stride;
-    const float *c = blk + level_offset(N, l - 1);
-    float a = c[(2 * j) * nc + 2 * i], b = c[(2 * j) * nc + 2 * i + 1];
-    float d = c[(2 * j + 1) * nc + 2 * i], e = c[(2 * j + 1) * nc + 2 * i + 1];
-    blk[level_offset(N, l) + j * nl + i] = fminf(fminf(a, b), fminf(d, e));
+    const float *c = blk + level_offset(N, l - 1);  // rows of every level have stride N
+    float a = c[(2 * j) * N + 2 * i], b = c[(2 * j) * N + 2 * i + 1];
+    float d = c[(2 * j + 1) * N + 2 * i], e = c[(2 * j + 1) * N + 2 * i + 1];
+    blk[level_offset(N, l) + j * N + i] = fminf(fminf(a, b), fminf(d, e));
 }
 
 __global__ void k_read_level(const float *__restrict__ pyr, float *__restrict__ out, int N, int l, int64_t stride,
@@ -115,7 +115,7 @@ __global__ void k_read_level(const float *__restrict__ pyr, float *__restrict__ 
     int64_t per = (int64_t)nl * nl;
     int64_t p = g / per;
     int k = (int)(g % per);
-    out[g] = pyr[p * stride + level_offset(N, l) + k];
+    out[g] = pyr[p * stride + level_offset(N, l) + (k / nl) * N + k % nl];
 }
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -44,12 +44,14 @@ struct GridDev {
     float inf;       // +INFINITY, set by the host (see min_nn)
 };
 
-// Offset of level l inside a probe block: 2 (N^2 - (N>>l)^2).  The gap between levels l and
-// l+1 is 1.5 (N>>l)^2 >= (N>>l)^2, so every level fits, the block is 2 N^2 floats, and
-// the offset needs only shifts (no integer multiply or divide in the march).
+// Layout of a probe's pyramid block (2 N^2 floats): every level keeps the row stride N of
+// level 0, so texel (i, j) of level l is at level_offset(N, l) + j N + i.  Level l holds
+// N >> l rows, N^2 >> l floats, and starts at 2 N^2 - (2 N^2 >> l): level 0 at 0, level 1
+// at N^2, level 2 at 1.5 N^2, ...  An address is then two shifts and adds, with no
+// per-level row stride in the march.
 __host__ __device__ __forceinline__ int level_offset(int N, int l) {
-    int NN = N * N;
-    return 2 * (NN - (NN >> (2 * l)));
+    int K = 2 * N * N;
+    return K - (K >> l);
 }
 
 // Texel `idx` (floats from the start of the pyramid); the byte offset fits 32 bits, so the
@@ -212,6 +214,18 @@ __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const f
     s.B1 = __fmaf_rn(b2, w[2], __fmaf_rn(b1, w[1], b0 * w[0]));
     s.L0 = __fmaf_rn(sz, Xp[2], __fmaf_rn(sy, Xp[1], sx * Xp[0]));
     s.L1 = __fmaf_rn(sz, w[2], __fmaf_rn(sy, w[1], sx * w[0]));
+    s.ts = ts;
+    s.te = te;
+    s.ilo = sx > 0.0f ? N / 2 : 0;
+    s.ihi = sx > 0.0f ? N - 1 : N / 2 - 1;
+    s.jlo = sy > 0.0f ? N / 2 : 0;
+    s.jhi = sy > 0.0f ? N - 1 : N / 2 - 1;
+}
+
+// What only the march needs (pieces the whole-piece test rejects skip it): the direction
+// of motion of x = A/L and y = B/L along the piece (sign of d/dt (A/L)), the sign-folded
+// crossing forms and the quadrant edges ahead.
+__device__ __forceinline__ void piece_motion(Piece &s) {
     float gx = __fmaf_rn(s.A1, s.L0, -(s.A0 * s.L1));
     float gy = __fmaf_rn(s.B1, s.L0, -(s.B0 * s.L1));
     s.dx = gx > 0.0f ? 1 : (gx < 0.0f ? -1 : 0);
@@ -225,12 +239,6 @@ __device__ __forceinline__ void piece_setup(Piece &s, const float Xp[3], const f
     s.Ly = fdy * s.L0;
     s.Py = fdy * s.B1;
     s.Ly1 = fdy * s.L1;
-    s.ts = ts;
-    s.te = te;
-    s.ilo = sx > 0.0f ? N / 2 : 0;
-    s.ihi = sx > 0.0f ? N - 1 : N / 2 - 1;
-    s.jlo = sy > 0.0f ? N / 2 : 0;
-    s.jhi = sy > 0.0f ? N - 1 : N / 2 - 1;
     s.ex = s.dx > 0 ? s.ihi + 1 : s.ilo;
     s.ey = s.dy > 0 ? s.jhi + 1 : s.jlo;
 }
@@ -263,29 +271,29 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
     const int N = g.N;
     int l = top;
     int I = i0 >> l, J = j0 >> l;
-    uint32_t off = base + (uint32_t)level_offset(N, l);
-    const uint32_t last = base + g.stride32 - 1u;
+    const uint32_t K = g.stride32;  // 2 N^2
+    const uint32_t baseK = base + K;
+    uint32_t off = baseK - (K >> l);  // base + level_offset(N, l)
+    const uint32_t last = base + K - 1u;
     float t = s.ts;
     float tx = next_x(s, I, l), ty = next_y(s, J, l);
-    const int guard = 24 * N + 64;
-    bool found = false;
-    // one exit: the loop state at the exit is the answer (the compiler then keeps the
-    // state in place instead of copying candidate outputs around the loop)
-    for (int it = 0; it < guard; ++it) {
+    // Exits: a level-0 fire (the answer: l stays 0), or a texel that does not fire and holds
+    // the end of the piece (l is set to -1).  Steps past texels are capped as a guard
+    // against a broken walk; between two steps there are at most `top` descents.
+    int guard = 24 * N + 64;
+    for (;;) {
         bool ax = tx <= ty, ay = ty <= tx;  // the axis (or both) whose boundary comes first
         float tmin = ax ? tx : ty;
         float texit = clamp_nn(tmin, t, s.te);  // t <= te throughout
         float re2 = rho2_at(Xp, w, texit);
         float m2 = max_pos(rc2, re2);
         // the index stays inside the probe block even if the walk were wrong
-        float M = pyr_at(g, min(off + ((uint32_t)J << (g.logN - l)) + (uint32_t)I, last));
+        float M = pyr_at(g, min(off + ((uint32_t)J << g.logN) + (uint32_t)I, last));
         // coarse levels test conservatively (the min over a parent must not miss a child
         // whose ray span's rho^2 rounds a little above the parent's endpoints)
         float lim = l == 0 ? m2 : m2 * 1.0000153f;
-        bool fire = below(M, lim);
-        found = fire & (l == 0);
-        if (found | (!fire & !(tmin < s.te))) break;  // level-0 fire, or the piece ends in this texel
-        if (fire) {
+        if (below(M, lim)) {
+            if (l == 0) break;
             // descend into the child that holds the ray point at t
             float iL = frcp(__fmaf_rn(t, s.L1, s.L0));
             float x = __fmaf_rn(t, s.A1, s.A0) * iL;
@@ -294,6 +302,10 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
             I = min(max((int)floorf(x) >> l, 2 * I), 2 * I + 1);
             J = min(max((int)floorf(y) >> l, 2 * J), 2 * J + 1);
         } else {
+            if (!(tmin < s.te) | (--guard < 0)) {  // the piece ends inside this texel
+                l = -1;
+                break;
+            }
             // step past the texel; a finite candidate implies the crossed boundary lies
             // inside the quadrant, so the stepped index stays in range.  Move up while the
             // step left the parent: the parents differ at every shift up to the highest
@@ -309,7 +321,7 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
             t = texit;
             rc2 = re2;
         }
-        off = base + (uint32_t)level_offset(N, l);
+        off = baseK - (K >> l);
         tx = next_x(s, I, l);
         ty = next_y(s, J, l);
     }
@@ -317,7 +329,7 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
     f.j = J;
     f.tin = t;
     f.rin2 = rc2;
-    return found;
+    return l == 0;
 }
 
 struct ProbeResult {
@@ -402,9 +414,8 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
             lv += ((bi1 >> lv) - (bi0 >> lv) > 1) | ((bj1 >> lv) - (bj0 >> lv) > 1);
             lv = min(lv, g.Lc - 1);
             uint32_t lev = base + (uint32_t)level_offset(N, lv);
-            int sh = g.logN - lv;
             uint32_t a = (uint32_t)(bi0 >> lv), b = (uint32_t)(bi1 >> lv);
-            uint32_t c = (uint32_t)(bj0 >> lv) << sh, d = (uint32_t)(bj1 >> lv) << sh;
+            uint32_t c = (uint32_t)(bj0 >> lv) << g.logN, d = (uint32_t)(bj1 >> lv) << g.logN;
             float lim = max_pos(rs2, rho2_at(Xp, w, hi)) * 1.0000153f;
             // each texel tested on its own: a texel without data (NaN) never fires
             miss = !(below(pyr_at(g, lev + c + a), lim) | below(pyr_at(g, lev + c + b), lim) |
@@ -427,7 +438,12 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
             j0 = min(max((int)floorf(ym), s.jlo), s.jhi);
         }
         Fire f;
-        if (!miss && march_piece(g, base, Xp, w, s, i0, j0, rs2, top, f)) {
+        bool fired = false;
+        if (!miss) {
+            piece_motion(s);
+            fired = march_piece(g, base, Xp, w, s, i0, j0, rs2, top, f);
+        }
+        if (fired) {
             int k = f.j * N + f.i;
             float r = pyr_at(g, base + (uint32_t)k);
             res.texel = k;
