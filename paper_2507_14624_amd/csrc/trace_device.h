@@ -387,18 +387,24 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         float hi = sgi == nc ? tb : (sgi == 0 ? c0 : (sgi == 1 ? c1 : c2));
         Piece s;
         piece_setup(s, Xp, w, lo, hi, N);
+        // the march starts from the texel of the start point; if the piece starts at the
+        // probe origin (L = 0 there), from the texel of its midpoint
+        float Ls0 = __fmaf_rn(lo, s.L1, s.L0);
         float xs, ys, Ls, xe, ye, Le;
-        piece_xy(s, Xp, w, lo, N, xs, ys, Ls);
+        piece_xy(s, Xp, w, Ls0 > 0.0f ? lo : 0.5f * (s.ts + s.te), N, xs, ys, Ls);
         piece_xy(s, Xp, w, hi, N, xe, ye, Le);
+        if (!(Ls > 0.0f)) {
+            xs = (float)s.ilo;
+            ys = (float)s.jlo;
+        }
+        int fxs = (int)floorf(xs), fys = (int)floorf(ys);
+        int i0 = min(max(fxs, s.ilo), s.ihi);
+        int j0 = min(max(fys, s.jlo), s.jhi);
         float rs2 = rho2_at(Xp, w, lo);
         bool miss = false;
         int top = g.top;
-        int i0, j0;  // level-0 texel where the march starts
-        if (Ls > 0.0f && Le > 0.0f) {
-            int fxs = (int)floorf(xs), fys = (int)floorf(ys);
+        if (Ls0 > 0.0f && Le > 0.0f) {
             int fxe = (int)floorf(xe), fye = (int)floorf(ye);
-            i0 = min(max(fxs, s.ilo), s.ihi);
-            j0 = min(max(fys, s.jlo), s.jhi);
             // O(1) MISS test of the whole piece: its projection is a straight segment, so the
             // texels it crosses lie in the box spanned by its end texels (widened by one texel
             // against rounding).  At the pyramid level where that box spans at most 2x2
@@ -422,20 +428,6 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
                      below(pyr_at(g, lev + d + a), lim) | below(pyr_at(g, lev + d + b), lim));
             // the whole piece fits 2x2 texels of level lv: no coarser level can skip more
             top = min(top, lv);
-        } else {
-            // an end of the piece is the probe origin: start from the texel of the start
-            // point, or of the midpoint if the start is the origin
-            float xm = xs, ym = ys;
-            if (!(Ls > 0.0f)) {
-                float Lm;
-                piece_xy(s, Xp, w, 0.5f * (s.ts + s.te), N, xm, ym, Lm);
-                if (!(Lm > 0.0f)) {
-                    xm = (float)s.ilo;
-                    ym = (float)s.jlo;
-                }
-            }
-            i0 = min(max((int)floorf(xm), s.ilo), s.ihi);
-            j0 = min(max((int)floorf(ym), s.jlo), s.jhi);
         }
         Fire f;
         bool fired = false;
