@@ -98,6 +98,10 @@ typedef struct {
 #define PT_FLAG_GRAPH 2u      /* capture the launch in a hipGraph and replay it on `stream`
                                  (implies PERSISTENT); the graph is cached per grid and
                                  rebuilt when views, pointers or options change */
+#define PT_FLAG_NEAREST 4u    /* radiance of the hit texel itself, as the appendix algorithms
+                                 fetch it (traceOneProbe, highResolutionTracing), instead of
+                                 the bilinear sample at the hit direction; the adjoint then
+                                 has one tap per HIT ray */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 

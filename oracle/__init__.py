@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("thickness_rel", ctypes.c_double), ("eye_eps_rel", ctypes.c_double),
                 ("background", ctypes.c_double * 3), ("delta", ctypes.c_double),
                 ("max_probes_per_cell", ctypes.c_int32), ("check_hier", ctypes.c_int32),
-                ("top_level", ctypes.c_int32), ("nthreads", ctypes.c_int32)]
+                ("top_level", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("nearest", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -205,7 +205,7 @@ def view_rays(pos, right, up, fwd, tan_half_fov_y, width, height, pixels=None):
 # ---------------------------------------------------------------------------------------------
 def default_opts(N: int, **kw) -> dict:
     o = dict(thickness_rel=8.0 / N, eye_eps_rel=1e-6, background=(0.0, 0.0, 0.0), delta=DEFAULT_DELTA,
-             max_probes_per_cell=8, check_hier=1, top_level=-1, nthreads=os.cpu_count() or 1)
+             max_probes_per_cell=8, check_hier=1, top_level=-1, nthreads=os.cpu_count() or 1, nearest=False)
     o.update(kw)
     return o
 
@@ -229,6 +229,7 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, **kw) -> dict:
     oo.check_hier = int(opts["check_hier"])
     oo.top_level = int(opts["top_level"])
     oo.nthreads = int(opts["nthreads"])
+    oo.nearest = int(bool(opts["nearest"]))
     res = dict(status=np.empty(n, np.uint8), t=np.empty(n, np.float64), rgb=np.empty((n, 3), np.float64),
                probe=np.empty(n, np.int32), texel=np.empty(n, np.int32), margin=np.empty(n, np.int32),
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),

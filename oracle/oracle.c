@@ -88,6 +88,9 @@ typedef struct {
     int32_t check_hier;    /* also run the hierarchical schedule and compare */
     int32_t top_level;     /* hierarchical start level, <0 = levels-1 */
     int32_t nthreads;
+    int32_t nearest;       /* radiance of the hit texel itself (the appendix algorithms fetch
+                              the colour of the texel the march stopped at) instead of the
+                              bilinear sample at the hit direction */
 } opts_t;
 
 typedef struct {
@@ -682,11 +685,15 @@ static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const
                 out->probe[ri] = p;
                 out->texel[ri] = pr.texel;
                 out->rank[ri] = ordinal * 8 + rk;
-                double uv[2];
-                oracle_oct_encode(pr.dirp, uv);
                 int idx[4];
                 double wt[4];
-                bilinear_taps(uv[0], uv[1], g->N, idx, wt);
+                if (o->nearest) {
+                    for (int k = 0; k < 4; ++k) { idx[k] = pr.texel; wt[k] = k == 0 ? 1.0 : 0.0; }
+                } else {
+                    double uv[2];
+                    oracle_oct_encode(pr.dirp, uv);
+                    bilinear_taps(uv[0], uv[1], g->N, idx, wt);
+                }
                 const float *R = g->rad + (int64_t)p * g->N * g->N * 3;
                 for (int ch = 0; ch < 3; ++ch) {
                     double acc = 0;

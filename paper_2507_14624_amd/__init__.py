@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libprobetrace.so")
 PT_MISS, PT_HIT, PT_UNKNOWN = 0, 1, 2
 PT_FLAG_PERSISTENT = 1
 PT_FLAG_GRAPH = 2
+PT_FLAG_NEAREST = 4
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_autotune", "pt_last_error")

@@ -413,11 +413,9 @@ PT_TRACE_KERNEL k_backward_view(GridDev g, ViewDev v, const uint32_t *__restrict
         if (r.status == ST_HIT) {
             int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
             float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
-            float u, vv;
-            oct_encode(r.q[0], r.q[1], r.q[2], u, vv);
             int idx[4];
             float wt[4];
-            bilinear_taps(u, vv, g.N, idx, wt);
+            hit_taps(g, r, idx, wt);
             int64_t base = (int64_t)r.probe * g.N * g.N;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -466,6 +464,7 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     float ms = std::min(g->desc.spacing[0], std::min(g->desc.spacing[1], g->desc.spacing[2]));
     d.eye_eps2 = (eps * ms) * (eps * ms);
     d.max_probes = (o.max_probes_per_cell < 1 || o.max_probes_per_cell > 8) ? 8 : o.max_probes_per_cell;
+    d.nearest = (o.flags & PT_FLAG_NEAREST) ? 1 : 0;
     return PT_OK;
 }
 

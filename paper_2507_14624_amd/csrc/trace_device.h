@@ -41,6 +41,7 @@ struct GridDev {
     float tau1;      // 1 + thickness
     float bg[3];
     int max_probes;
+    int nearest;     // radiance of the hit texel itself instead of the bilinear sample
     float inf;       // +INFINITY, set by the host (see min_nn)
 };
 
@@ -640,13 +641,27 @@ __device__ __forceinline__ void camera_ray(const ViewDev &v, int x, int y, float
     w[2] = d2 * inv;
 }
 
-// Radiance of a HIT: bilinear fetch of the hit probe's map in the direction of the hit
-// point; also returns the taps for the adjoint.
-__device__ __forceinline__ void hit_radiance(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult &r,
-                                             float rgb[3], int idx[4], float wt[4]) {
+// Radiance taps of a HIT: bilinear at the direction of the hit point (octahedral border
+// wrap), or, with `nearest`, the hit texel alone (the appendix algorithms fetch the colour
+// of the texel the march stopped at).
+__device__ __forceinline__ void hit_taps(const GridDev &g, const RayResult &r, int idx[4], float wt[4]) {
+    if (g.nearest) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            idx[k] = r.texel;
+            wt[k] = k == 0 ? 1.0f : 0.0f;
+        }
+        return;
+    }
     float u, v;
     oct_encode(r.q[0], r.q[1], r.q[2], u, v);
     bilinear_taps(u, v, g.N, idx, wt);
+}
+
+// Radiance of a HIT from its taps; also returns the taps for the adjoint.
+__device__ __forceinline__ void hit_radiance(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult &r,
+                                             float rgb[3], int idx[4], float wt[4]) {
+    hit_taps(g, r, idx, wt);
     const uint16_t *R = rad + (int64_t)r.probe * g.N * g.N * 3;
     rgb[0] = rgb[1] = rgb[2] = 0.0f;
 #pragma unroll

@@ -242,8 +242,15 @@ class ProbeSet:
         return self.radiance.view(np.float16).astype(np.float32)
 
 
-def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None) -> ProbeSet:
-    """Bake every probe of ``scene`` at N x N texels (centre-ray nearest surface)."""
+def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals: str = "geometric") -> ProbeSet:
+    """Bake every probe of ``scene`` at N x N texels (centre-ray nearest surface).
+
+    normals: "geometric" stores the surface's outward normal; "incoming" stores, as the
+    paper's probe data generation literally does, the direction from the probe to the
+    stored point (for a centre-ray bake, the texel's own centre direction, whose octahedral
+    coordinates are the texel centre)."""
+    if normals not in ("geometric", "incoming"):
+        raise ValueError(normals)
     lib = _load()
     P = scene.n_probes
     pos = np.ascontiguousarray(scene.probe_positions())
@@ -255,6 +262,10 @@ def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None) -> Prob
     lib.synth_bake(_dp(scene.room_max), _dp(scene.wall_albedo), int(len(scene.obj_type)),
                    _ip(scene.obj_type), _dp(scene.obj_param), _dp(scene.obj_albedo), P, _dp(pos), int(N),
                    _fp(dist), _fp(nrm), _fp(rad), _ip(sid), int(nt))
+    if normals == "incoming":
+        c = (-1.0 + (2.0 * np.arange(N) + 1.0) / N).astype(np.float32)
+        nrm[..., 0] = c[None, None, :]
+        nrm[..., 1] = c[None, :, None]
     f32 = lambda v: np.array(v, dtype=np.float32)
     return ProbeSet(
         dims=tuple(scene.dims), origin=f32([scene.origin] * 3), spacing=f32([scene.spacing] * 3), N=int(N),

@@ -32,22 +32,23 @@ def _setup(name, **kw):
     return pt, scene, probes, views, grid, rad
 
 
-def _check_grad(pt, probes, grid, rad, views, seed=0):
+def _check_grad(pt, probes, grid, rad, views, seed=0, nearest=False):
     og = oracle.Grid.from_probes(probes)
-    res = pt.probe_trace(grid, rad, views)
+    opts = pt.trace_opts(flags=pt.PT_FLAG_NEAREST) if nearest else None
+    res = pt.probe_trace(grid, rad, views, opts)
     res = {k: v.cpu().numpy() for k, v in res.items()}
     o_parts, d_parts = [], []
     for v in views:
         o, d = oracle.view_rays(*v.as_tuple())
         o_parts.append(o)
         d_parts.append(d)
-    orc = oracle.trace(og, np.concatenate(o_parts), np.concatenate(d_parts))
+    orc = oracle.trace(og, np.concatenate(o_parts), np.concatenate(d_parts), nearest=nearest)
     s = compare(res, orc)
     rng = np.random.default_rng(seed)
     g = rng.normal(size=(s["n"], 3)).astype(np.float32)
     g[s["disagree_idx"]] = 0.0
     gg = torch.zeros((probes.n_probes, probes.N, probes.N, 3), dtype=torch.float32, device="cuda")
-    pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gg)
+    pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gg, opts)
     got = gg.cpu().numpy().astype(np.float64)
     ref = oracle.vjp(og, orc, g.astype(np.float64))
     wabs = oracle.vjp(og, orc, np.abs(g).astype(np.float64))
@@ -73,6 +74,12 @@ def test_backward_matches_oracle_vjp_tiny():
 def test_backward_matches_oracle_vjp_room_views():
     pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=2, size=(96, 80))
     _check_grad(pt, probes, grid, rad, views)
+
+
+def test_backward_nearest_texel_radiance():
+    # one tap per HIT ray: the gradient of a texel is the sum of its rays' grad_rgb
+    pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=2, size=(96, 80))
+    _check_grad(pt, probes, grid, rad, views, nearest=True)
 
 
 def test_backward_accumulates():

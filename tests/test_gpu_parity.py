@@ -171,12 +171,37 @@ def test_parity_options():
     scene, probes, views, grid, rad = _grid("tiny")
     og = _oracle_grid(probes)
     v = views[0]
+    # the paper-literal variants (two cage probes per cell; no shadow-entry rule, i.e. the
+    # appendix classification as printed; the hit texel's own radiance) and plain options
     for kw in (dict(max_probes_per_cell=2), dict(thickness_rel=0.02), dict(thickness_rel=float("inf")),
-               dict(background=(0.25, 0.5, 1.0))):
-        res = _gpu_numpy(pt.probe_trace(grid, rad, [v], pt.trace_opts(**kw)))
-        okw = dict(kw)
-        orc = oracle.trace_view(og, v.as_tuple(), **okw)
+               dict(background=(0.25, 0.5, 1.0)), dict(nearest=True),
+               dict(nearest=True, thickness_rel=float("inf"), max_probes_per_cell=2)):
+        gkw = {k: val for k, val in kw.items() if k != "nearest"}
+        if kw.get("nearest"):
+            gkw["flags"] = pt.PT_FLAG_NEAREST
+        res = _gpu_numpy(pt.probe_trace(grid, rad, [v], pt.trace_opts(**gkw)))
+        orc = oracle.trace_view(og, v.as_tuple(), **kw)
         assert_parity(compare(res, orc), f"tiny {kw}")
+        if kw.get("nearest"):
+            # exactly the stored FP16 radiance of the hit texel
+            h = res["status"] == oracle.HIT
+            R = probes.radiance.view(np.float16).astype(np.float32).reshape(probes.n_probes, -1, 3)
+            assert np.array_equal(res["rgb"][h], R[res["hit"][h, 0], res["hit"][h, 1]])
+
+
+def test_parity_incoming_direction_normal_maps():
+    # the literal normal maps of the probe data generation (probe-to-point directions)
+    import synth
+    pt = _pt()
+    scene, probes, views = workload("single", size=(240, 135))
+    lit = synth.bake(scene, probes.N, probes.levels, normals="incoming")
+    grid = pt.ProbeGrid.from_probes(lit)
+    rad = torch.from_numpy(lit.radiance.view(np.float16).copy()).cuda()
+    res = _gpu_numpy(pt.probe_trace(grid, rad, [views[0]]))
+    orc = oracle.trace_view(_oracle_grid(lit), views[0].as_tuple())
+    s = compare(res, orc)
+    assert_parity(s, "room 240x135, incoming-direction normals")
+    assert 0.05 < s["hit_frac"] < 0.95
 
 
 def _batch_views(k=6, shrink=8):
