@@ -98,6 +98,8 @@ typedef struct {
 #define PT_FLAG_GRAPH 2u      /* capture the launch in a hipGraph and replay it on `stream`
                                  (implies PERSISTENT); the graph is cached per grid and
                                  rebuilt when views, pointers or options change */
+#define PT_FLAG_WIDE 8u       /* 64-bit probe addressing even for grids below 4 GiB of pyramid
+                                 (it is used by itself above); results are identical */
 #define PT_FLAG_NEAREST 4u    /* radiance of the hit texel itself, as the appendix algorithms
                                  fetch it (traceOneProbe, highResolutionTracing), instead of
                                  the bilinear sample at the hit direction; the adjoint then
@@ -115,6 +117,20 @@ void pt_trace_opts_default(pt_trace_opts *opts);
  * OUT_OF_MEMORY, HIP. */
 pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev, const uint16_t *normal_oct_dev,
                             void *stream, pt_grid **out);
+
+/* Two-level probe hierarchy (the paper's hierarchical scene representation, teaser and
+ * Large Scale Scene Reconstruction; the paper gives no algorithm, this is our reading):
+ * attach `coarse` as the coarse level of `fine`.  The coarse grid's cell planes must be
+ * fine planes: coarse plane k of axis a is fine plane plane_off[a] + k * ratio[a] (checked
+ * on the origins and spacings to 1e-5), so every fine cell lies in exactly one coarse cell.
+ * A trace of `fine` then tries, in each fine cell's interval, the fine cage first and then
+ * the cage of that coarse cell over the same interval; the first HIT wins.  Coarse probe p
+ * is probe P_fine + p everywhere: in hit_dev, in radiance_dev ([P_fine + P_coarse][N][N][3],
+ * fine first) and in grad_radiance_dev.  Both levels need the same map resolution N.  The
+ * caller keeps `coarse` alive while attached; coarse = NULL detaches.  Errors:
+ * INVALID_ARGUMENT (NULL fine grid, mismatched planes or N, coarse itself two-level). */
+pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse, const int32_t plane_off[3],
+                                const int32_t ratio[3]);
 
 /* Free a grid (synchronises the device first).  NULL is ignored. */
 void probe_grid_destroy(pt_grid *grid);

@@ -210,7 +210,11 @@ def default_opts(N: int, **kw) -> dict:
     return o
 
 
-def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, **kw) -> dict:
+class _Level2(ctypes.Structure):
+    _fields_ = [("coarse", ctypes.c_void_p), ("plane_off", ctypes.c_int32 * 3), ("ratio", ctypes.c_int32 * 3)]
+
+
+def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) -> dict:
     """Trace rays; returns per-ray arrays (status, t, rgb, probe, texel, margin, tests,
     normals, flat_tests, rank, taps, wts, score, work).  ``score`` is the smallest gap/error-scale
     ratio over the ray's decisions; ``margin`` has a bit per decision kind with ratio <= delta;
@@ -239,7 +243,19 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, **kw) -> dict:
     for k, v in res.items():
         setattr(out, k, v.ctypes.data)
     g = grid._struct()
-    lib.oracle_trace(ctypes.byref(g), ctypes.byref(oo), n, _ptr(o), _ptr(d), ctypes.byref(out))
+    if coarse is None:
+        lib.oracle_trace(ctypes.byref(g), ctypes.byref(oo), n, _ptr(o), _ptr(d), ctypes.byref(out))
+    else:
+        # two-level hierarchy: coarse = (coarse Grid, plane_off[3], ratio[3]); coarse plane a
+        # is fine plane plane_off + a * ratio; coarse probe p is reported as P_fine + p
+        cgrid, off, ratio = coarse
+        cs = cgrid._struct()
+        L2 = _Level2()
+        L2.coarse = ctypes.addressof(cs)
+        L2.plane_off[:] = [int(x) for x in off]
+        L2.ratio[:] = [int(x) for x in ratio]
+        lib.oracle_trace2(ctypes.byref(g), ctypes.byref(L2), ctypes.byref(oo), n, _ptr(o), _ptr(d),
+                          ctypes.byref(out))
     return res
 
 
@@ -248,12 +264,13 @@ def trace_view(grid: Grid, view, pixels=None, **kw) -> dict:
     return trace(grid, o, d, **kw)
 
 
-def vjp(grid: Grid, result: dict, grad_rgb: np.ndarray) -> np.ndarray:
+def vjp(grid, result: dict, grad_rgb: np.ndarray) -> np.ndarray:
     """Adjoint of the radiance fetch with the hit test held fixed (an extension beyond the paper, which renders forward only):
     dL/dRad[p][tap][c] = sum over HIT rays of w_tap * dL/drgb[c].  Accumulated in double,
     duplicate taps add up."""
-    P = grid.distance.shape[0]
-    N = grid.N
+    grids = grid if isinstance(grid, (list, tuple)) else (grid,)  # (fine, coarse): probes concatenated
+    P = sum(gr.distance.shape[0] for gr in grids)
+    N = grids[0].N
     g = np.zeros((P * N * N, 3), dtype=np.float64)
     hit = result["status"] == HIT
     if not np.any(hit):

@@ -93,6 +93,19 @@ typedef struct {
                               bilinear sample at the hit direction */
 } opts_t;
 
+/* Two-level probe hierarchy (the paper's hierarchical scene representation; no algorithm
+ * is given, this is our reading): a fine grid and a coarse grid whose cell planes are a
+ * subset of the fine grid's, coarse plane a = fine plane plane_off + a * ratio per axis, so
+ * every fine cell (outer clamped cells included) lies in exactly one coarse cell.  In each
+ * fine cell's interval [ta, tb] the fine cage is traced first, then the cage of the coarse
+ * cell holding that fine cell, over the same interval; the first HIT wins.  Coarse probe p
+ * is reported as probe P_fine + p. */
+typedef struct {
+    const void *coarse;     /* grid_t of the coarse level, NULL = one level */
+    int32_t plane_off[3];
+    int32_t ratio[3];
+} level2_t;
+
 typedef struct {
     uint8_t *status;   /* [n] */
     double *t;         /* [n] hit distance from the camera (+inf if none) */
@@ -590,8 +603,28 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
 /* ------------------------------------------------------------------------------------
  * One camera ray: grid iterator over cells, closest-first cage probes, fall-through.
  * ------------------------------------------------------------------------------------ */
-static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const double win[3], out_t *out,
-                      int64_t ri) {
+/* the 8 corner probes of a cell, closest to the eye first, ties by corner code */
+static void cage_sort(const grid_t *g, const int cell[3], const double X[3], int code[8], double dd[8]) {
+    for (int c = 0; c < 8; ++c) {
+        int ci = cell[0] + (c & 1), cj = cell[1] + ((c >> 1) & 1), ck = cell[2] + (c >> 2);
+        double d2 = 0;
+        double O[3] = {g->origin[0] + ci * g->spacing[0], g->origin[1] + cj * g->spacing[1],
+                       g->origin[2] + ck * g->spacing[2]};
+        for (int a = 0; a < 3; ++a) d2 += (O[a] - X[a]) * (O[a] - X[a]);
+        code[c] = c;
+        dd[c] = sqrt(d2);
+    }
+    for (int a = 1; a < 8; ++a) /* insertion sort, stable: ties keep corner-code order */
+        for (int b = a; b > 0 && dd[b] < dd[b - 1]; --b) {
+            double td = dd[b]; dd[b] = dd[b - 1]; dd[b - 1] = td;
+            int tc = code[b]; code[b] = code[b - 1]; code[b - 1] = tc;
+        }
+}
+
+static inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, const double X[3], const double win[3],
+                      out_t *out, int64_t ri) {
     double w[3];
     double wl = sqrt(win[0] * win[0] + win[1] * win[1] + win[2] * win[2]);
     for (int a = 0; a < 3; ++a) w[a] = win[a] / wl;
@@ -647,64 +680,61 @@ static void trace_ray(const grid_t *g, const opts_t *o, const double X[3], const
             for (int b = a + 1; b < 3; ++b)
                 if (isfinite(tn[b])) decide(&mc, tn[a] - tn[b], En[a] + En[b], MG_CELL);
         }
-        /* cage: the 8 corner probes, closest to the eye first, ties by corner code */
-        int code[8];
-        double dd[8];
-        for (int c = 0; c < 8; ++c) {
-            int ci = cell[0] + (c & 1), cj = cell[1] + ((c >> 1) & 1), ck = cell[2] + (c >> 2);
-            double d2 = 0;
-            double O[3] = {g->origin[0] + ci * g->spacing[0], g->origin[1] + cj * g->spacing[1],
-                           g->origin[2] + ck * g->spacing[2]};
-            for (int a = 0; a < 3; ++a) d2 += (O[a] - X[a]) * (O[a] - X[a]);
-            code[c] = c;
-            dd[c] = sqrt(d2);
-        }
-        for (int a = 1; a < 8; ++a) /* insertion sort, stable: ties keep corner-code order */
-            for (int b = a; b > 0 && dd[b] < dd[b - 1]; --b) {
-                double td = dd[b]; dd[b] = dd[b - 1]; dd[b - 1] = td;
-                int tc = code[b]; code[b] = code[b - 1]; code[b - 1] = tc;
-            }
-        for (int rk = 0; rk < mp; ++rk) {
-            int c = code[rk];
-            int p = (cell[0] + (c & 1)) +
-                    g->dims[0] * ((cell[1] + ((c >> 1) & 1)) + g->dims[1] * (cell[2] + (c >> 2)));
-            presult_t pr;
-            trace_one_probe(g, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
-            ++n_probe;
-            n_piece += pr.pieces;
-            tests += pr.tests;
-            normals += pr.normals;
-            flat_tests += pr.flat_tests;
-            if (pr.status == ST_HIT) {
-                /* the order only mattered if the resolving probe nearly tied with a neighbour */
-                double cs = 8.0 * (dd[rk] + 4.0 * g->spacing[0]);
-                if (rk + 1 < mp) decide(&mc, dd[rk + 1] - dd[rk], cs, MG_CAGE);
-                if (rk > 0) decide(&mc, dd[rk] - dd[rk - 1], cs, MG_CAGE);
-                out->status[ri] = ST_HIT;
-                out->t[ri] = pr.t;
-                out->probe[ri] = p;
-                out->texel[ri] = pr.texel;
-                out->rank[ri] = ordinal * 8 + rk;
-                int idx[4];
-                double wt[4];
-                if (o->nearest) {
-                    for (int k = 0; k < 4; ++k) { idx[k] = pr.texel; wt[k] = k == 0 ? 1.0 : 0.0; }
-                } else {
-                    double uv[2];
-                    oracle_oct_encode(pr.dirp, uv);
-                    bilinear_taps(uv[0], uv[1], g->N, idx, wt);
+        const grid_t *cg = L2 && L2->coarse ? (const grid_t *)L2->coarse : NULL;
+        int ccell[3] = {0, 0, 0};
+        if (cg)
+            for (int a = 0; a < 3; ++a)
+                ccell[a] = clampi(floordiv(cell[a] - L2->plane_off[a], L2->ratio[a]), 0, cg->dims[a] - 2);
+        const int Pf = g->dims[0] * g->dims[1] * g->dims[2];
+        for (int lev = 0; lev < (cg ? 2 : 1); ++lev) {
+            const grid_t *G = lev == 0 ? g : cg;
+            const int *cl = lev == 0 ? cell : ccell;
+            /* cage: the 8 corner probes, closest to the eye first, ties by corner code */
+            int code[8];
+            double dd[8];
+            cage_sort(G, cl, X, code, dd);
+            for (int rk = 0; rk < mp; ++rk) {
+                int c = code[rk];
+                int p = (cl[0] + (c & 1)) +
+                        G->dims[0] * ((cl[1] + ((c >> 1) & 1)) + G->dims[1] * (cl[2] + (c >> 2)));
+                presult_t pr;
+                trace_one_probe(G, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
+                ++n_probe;
+                n_piece += pr.pieces;
+                tests += pr.tests;
+                normals += pr.normals;
+                flat_tests += pr.flat_tests;
+                if (pr.status == ST_HIT) {
+                    /* the order only mattered if the resolving probe nearly tied with a neighbour */
+                    double cs = 8.0 * (dd[rk] + 4.0 * G->spacing[0]);
+                    if (rk + 1 < mp) decide(&mc, dd[rk + 1] - dd[rk], cs, MG_CAGE);
+                    if (rk > 0) decide(&mc, dd[rk] - dd[rk - 1], cs, MG_CAGE);
+                    out->status[ri] = ST_HIT;
+                    out->t[ri] = pr.t;
+                    out->probe[ri] = lev == 0 ? p : Pf + p;
+                    out->texel[ri] = pr.texel;
+                    out->rank[ri] = cg ? ordinal * 16 + lev * 8 + rk : ordinal * 8 + rk;
+                    int idx[4];
+                    double wt[4];
+                    if (o->nearest) {
+                        for (int k = 0; k < 4; ++k) { idx[k] = pr.texel; wt[k] = k == 0 ? 1.0 : 0.0; }
+                    } else {
+                        double uv[2];
+                        oracle_oct_encode(pr.dirp, uv);
+                        bilinear_taps(uv[0], uv[1], G->N, idx, wt);
+                    }
+                    const float *R = G->rad + (int64_t)p * G->N * G->N * 3;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        double acc = 0;
+                        for (int k = 0; k < 4; ++k) acc += wt[k] * (double)R[3 * idx[k] + ch];
+                        out->rgb[3 * ri + ch] = acc;
+                    }
+                    if (out->taps)
+                        for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
+                    goto done;
                 }
-                const float *R = g->rad + (int64_t)p * g->N * g->N * 3;
-                for (int ch = 0; ch < 3; ++ch) {
-                    double acc = 0;
-                    for (int k = 0; k < 4; ++k) acc += wt[k] * (double)R[3 * idx[k] + ch];
-                    out->rgb[3 * ri + ch] = acc;
-                }
-                if (out->taps)
-                    for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
-                goto done;
+                if (pr.status == ST_UNKNOWN) any_unknown = 1;
             }
-            if (pr.status == ST_UNKNOWN) any_unknown = 1;
         }
         if (tb >= tfar) break;
         for (int a = 0; a < 3; ++a)
@@ -738,6 +768,7 @@ done:
  * ------------------------------------------------------------------------------------ */
 typedef struct {
     const grid_t *g;
+    const level2_t *L2;
     const opts_t *o;
     const double *orig, *dir;
     int64_t n;
@@ -751,15 +782,18 @@ static void *worker(void *arg) {
         int64_t b = atomic_fetch_add(&jb->next, 256);
         if (b >= jb->n) break;
         int64_t e = b + 256 < jb->n ? b + 256 : jb->n;
-        for (int64_t i = b; i < e; ++i) trace_ray(jb->g, jb->o, jb->orig + 3 * i, jb->dir + 3 * i, jb->out, i);
+        for (int64_t i = b; i < e; ++i)
+            trace_ray(jb->g, jb->L2, jb->o, jb->orig + 3 * i, jb->dir + 3 * i, jb->out, i);
     }
     return NULL;
 }
 
-int oracle_trace(const grid_t *g, const opts_t *o, int64_t n, const double *orig, const double *dir, out_t *out) {
+/* Trace n rays; L2 (nullable) adds the coarse level of a two-level hierarchy. */
+int oracle_trace2(const grid_t *g, const level2_t *L2, const opts_t *o, int64_t n, const double *orig,
+                  const double *dir, out_t *out) {
     int nt = o->nthreads < 1 ? 1 : (o->nthreads > 256 ? 256 : o->nthreads);
     job_t jb;
-    jb.g = g; jb.o = o; jb.orig = orig; jb.dir = dir; jb.n = n; jb.out = out;
+    jb.g = g; jb.L2 = L2; jb.o = o; jb.orig = orig; jb.dir = dir; jb.n = n; jb.out = out;
     atomic_init(&jb.next, 0);
     if (nt == 1) {
         worker(&jb);
@@ -769,6 +803,10 @@ int oracle_trace(const grid_t *g, const opts_t *o, int64_t n, const double *orig
     for (int i = 0; i < nt; ++i) pthread_create(&th[i], NULL, worker, &jb);
     for (int i = 0; i < nt; ++i) pthread_join(th[i], NULL);
     return 0;
+}
+
+int oracle_trace(const grid_t *g, const opts_t *o, int64_t n, const double *orig, const double *dir, out_t *out) {
+    return oracle_trace2(g, NULL, o, n, orig, dir, out);
 }
 
 /* ------------------------------------------------------------------------------------

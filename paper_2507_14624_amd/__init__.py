@@ -22,8 +22,10 @@ PT_MISS, PT_HIT, PT_UNKNOWN = 0, 1, 2
 PT_FLAG_PERSISTENT = 1
 PT_FLAG_GRAPH = 2
 PT_FLAG_NEAREST = 4
+PT_FLAG_WIDE = 8
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
+            "probe_grid_set_coarse",
             "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_autotune", "pt_last_error")
 
 
@@ -68,11 +70,12 @@ def load_library(path: str = LIB_PATH):
     lib.probe_grid_destroy.argtypes = [vp]
     lib.probe_grid_destroy.restype = None
     lib.probe_grid_read_level.argtypes = [vp, i32, vp, vp]
+    lib.probe_grid_set_coarse.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.probe_trace.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_backward.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_autotune.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, ctypes.POINTER(PtTraceOpts), vp]
-    for name in ("probe_grid_create", "probe_grid_read_level", "probe_trace", "probe_trace_rays",
+    for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_trace", "probe_trace_rays",
                  "probe_trace_backward", "probe_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
@@ -161,6 +164,7 @@ class ProbeGrid:
         self.handle = ctypes.c_void_p()
         self.desc = d
         self.P, self.N, self.levels = P, N, d.mip_levels
+        self.coarse = None
         self.dims = tuple(d.dims)
         self.device = distance.device
         _check(lib.probe_grid_create(ctypes.byref(d), _ptr(distance), _ptr(normal_half), _stream(stream),
@@ -176,6 +180,27 @@ class ProbeGrid:
         nrm = torch.from_numpy(np.ascontiguousarray(probes.normal).view(np.float16)).to(device)
         return cls(probes.dims, probes.origin, probes.spacing, probes.N, probes.levels, probes.scene_min,
                    probes.scene_max, dist, nrm)
+
+    @classmethod
+    def from_two_level(cls, two_level, device="cuda"):
+        """Fine grid with its coarse level attached, from a synth.TwoLevel pair."""
+        fine = cls.from_probes(two_level.fine, device)
+        fine.set_coarse(cls.from_probes(two_level.coarse, device), two_level.plane_off, two_level.ratio)
+        return fine
+
+    def set_coarse(self, coarse, plane_off=(0, 0, 0), ratio=(1, 1, 1)):
+        """Attach (or, with None, detach) the coarse level of a two-level hierarchy: coarse plane
+        k is fine plane plane_off + k * ratio.  Coarse probe p becomes probe self.P + p."""
+        lib = load_library()
+        off = (ctypes.c_int32 * 3)(*[int(x) for x in plane_off])
+        rat = (ctypes.c_int32 * 3)(*[int(x) for x in ratio])
+        _check(lib.probe_grid_set_coarse(self.handle, coarse.handle if coarse is not None else None, off, rat))
+        self.coarse = coarse  # keeps it alive while attached
+
+    @property
+    def P_total(self) -> int:
+        """Probes of the radiance layout: the fine ones, then the coarse level's."""
+        return self.P + (self.coarse.P if self.coarse is not None else 0)
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -203,6 +228,12 @@ def _alloc_outputs(rays, device, want_t=True, want_status=True, want_hit=True):
     return rgb, t, st, hit
 
 
+def _need(t, n: int, what: str):
+    """The library reads and writes these buffers by plain pointer: check their sizes here."""
+    if t is not None and t.numel() != n:
+        raise ProbeTraceError(f"{what}: expected {n} elements, got {t.numel()}")
+
+
 def probe_trace(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None = None, out=None, stream=None,
                 want_t=True, want_status=True, want_hit=True):
     """Trace every pixel of ``views``; returns dict(rgb, t, status, hit) of device tensors."""
@@ -210,8 +241,11 @@ def probe_trace(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None 
     radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
     va = views if isinstance(views, ctypes.Array) else make_views(views)
     rays = sum(v.width * v.height for v in va)
+    _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
     rgb, t, st, hit = out if out is not None else _alloc_outputs(rays, radiance_half.device, want_t, want_status,
                                                                   want_hit)
+    for a, k, what in ((rgb, 3, "rgb"), (t, 1, "t"), (st, 1, "status"), (hit, 2, "hit")):
+        _need(a, rays * k, what)
     _check(lib.probe_trace(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), _ptr(t), _ptr(st), _ptr(hit),
                            ctypes.byref(opts) if opts is not None else None, _stream(stream)))
     return dict(rgb=rgb, t=t, status=st, hit=hit)
@@ -223,6 +257,9 @@ def probe_trace_rays(grid: ProbeGrid, radiance_half, origins, dirs, opts: PtTrac
     origins = _dev_tensor(origins, torch.float32, "origins")
     dirs = _dev_tensor(dirs, torch.float32, "dirs")
     n = origins.shape[0]
+    _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
+    _need(origins, 3 * n, "origins")
+    _need(dirs, 3 * n, "dirs")
     rgb, t, st, hit = _alloc_outputs(n, origins.device)
     _check(lib.probe_trace_rays(grid.handle, _ptr(radiance_half), _ptr(origins), _ptr(dirs), int(n), _ptr(rgb),
                                 _ptr(t), _ptr(st), _ptr(hit), ctypes.byref(opts) if opts is not None else None,
@@ -237,6 +274,8 @@ def probe_trace_backward(grid: ProbeGrid, views, grad_rgb, grad_radiance, opts: 
     grad_rgb = _dev_tensor(grad_rgb, torch.float32, "grad_rgb")
     grad_radiance = _dev_tensor(grad_radiance, torch.float32, "grad_radiance")
     va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _need(grad_rgb, 3 * sum(v.width * v.height for v in va), "grad_rgb")
+    _need(grad_radiance, grid.P_total * grid.N * grid.N * 3, "grad_radiance")
     _check(lib.probe_trace_backward(grid.handle, va, len(va), _ptr(grad_rgb), _ptr(grad_radiance),
                                     ctypes.byref(opts) if opts is not None else None, _stream(stream)))
     return grad_radiance
@@ -248,6 +287,8 @@ def probe_autotune(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | No
     opts = opts if opts is not None else trace_opts()
     va = views if isinstance(views, ctypes.Array) else make_views(views)
     rays = sum(v.width * v.height for v in va)
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
     rgb = torch.empty((rays, 3), dtype=torch.float32, device=radiance_half.device)
     _check(lib.probe_autotune(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), ctypes.byref(opts),
                               _stream(stream)))

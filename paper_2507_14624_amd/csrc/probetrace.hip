@@ -52,6 +52,7 @@ struct GraphCache {
     std::vector<unsigned char> key;
     ViewDev *views_dev = nullptr;
     uint32_t *cage = nullptr;       // cage-order table of the captured views
+    uint32_t *ccage = nullptr;      // the same for the coarse level
     int cap = 0;
     hipStream_t capture = nullptr;  // private stream the graph is captured on
 };
@@ -75,6 +76,12 @@ struct pt_grid {
     int cells = 0;
     GraphCache graph;
     int num_cus = 256;
+    bool wide = false;  // pyramid of 4 GiB or more: 64-bit probe addressing
+    // coarse level of a two-level hierarchy (not owned) and its plane correspondence
+    const pt_grid *coarse = nullptr;
+    int off[3] = {0, 0, 0}, ratio[3] = {1, 1, 1};
+    uint32_t *ccage = nullptr;  // per-view cage-order tables of the coarse cells
+    int64_t ccage_cap = 0;
 };
 
 // ------------------------------------------------------------------------------------
@@ -154,9 +161,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: mip_levels must satisfy N >> (L-1) >= 2");
     int64_t P = (int64_t)desc->dims[0] * desc->dims[1] * desc->dims[2];
     if (P > (1 << 24)) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: too many probes");
-    // the trace addresses the pyramid (2 N^2 floats per probe) with 32-bit byte offsets
-    if (P * 2 * (int64_t)N * N * (int64_t)sizeof(float) > (int64_t)UINT32_MAX)
-        return fail(PT_ERR_UNSUPPORTED, "probe_grid_create: probes x 8 N^2 bytes must stay below 4 GiB");
+
     pt_grid *g = new (std::nothrow) pt_grid();
     if (!g) return fail(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: host allocation");
     g->desc = *desc;
@@ -164,6 +169,9 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     g->N = N;
     g->L = L;
     g->stride = 2 * (int64_t)N * N;
+    // the narrow trace addresses the whole pyramid (2 N^2 floats per probe) with 32-bit byte
+    // offsets; larger grids take the 64-bit path
+    g->wide = P * g->stride * (int64_t)sizeof(float) > (int64_t)UINT32_MAX;
     g->Lc = 0;
     while ((2 << g->Lc) <= N) ++g->Lc;  // levels down to 2x2 (log2 N of them)
     g->cells = (desc->dims[0] - 1) * (desc->dims[1] - 1) * (desc->dims[2] - 1);
@@ -202,7 +210,9 @@ extern "C" void probe_grid_destroy(pt_grid *g) {
     if (g->graph.graph) (void)hipGraphDestroy(g->graph.graph);
     if (g->graph.views_dev) (void)hipFree(g->graph.views_dev);
     if (g->graph.cage) (void)hipFree(g->graph.cage);
+    if (g->graph.ccage) (void)hipFree(g->graph.ccage);
     if (g->cage) (void)hipFree(g->cage);
+    if (g->ccage) (void)hipFree(g->ccage);
     if (g->graph.capture) (void)hipStreamDestroy(g->graph.capture);
     if (g->pyr) (void)hipFree(g->pyr);
     if (g->nrm) (void)hipFree(g->nrm);
@@ -211,6 +221,38 @@ extern "C" void probe_grid_destroy(pt_grid *g) {
     if (g->views_host) (void)hipHostFree(g->views_host);
     if (g->staging_free) (void)hipEventDestroy(g->staging_free);
     delete g;
+}
+
+extern "C" pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse, const int32_t plane_off[3],
+                                           const int32_t ratio[3]) {
+    if (!fine) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: NULL fine grid");
+    if (!coarse) {
+        fine->coarse = nullptr;
+        return PT_OK;
+    }
+    if (coarse == fine || coarse->coarse)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: the coarse level must be a plain grid");
+    if (!plane_off || !ratio) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: NULL plane map");
+    if (coarse->N != fine->N)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: both levels need the same map resolution");
+    if (coarse->device != fine->device)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: levels on different devices");
+    for (int a = 0; a < 3; ++a) {
+        if (ratio[a] < 1) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: ratio must be >= 1");
+        // coarse plane k must be fine plane plane_off + k ratio
+        double fs = fine->desc.spacing[a], fo = fine->desc.origin[a];
+        double want_o = fo + plane_off[a] * fs, want_s = ratio[a] * fs;
+        double tol = 1e-5 * (std::fabs(want_o) + want_s);
+        if (std::fabs(coarse->desc.origin[a] - want_o) > tol || std::fabs(coarse->desc.spacing[a] - want_s) > tol)
+            return fail(PT_ERR_INVALID_ARGUMENT,
+                        "probe_grid_set_coarse: coarse planes are not fine planes plane_off + k * ratio");
+    }
+    fine->coarse = coarse;
+    for (int a = 0; a < 3; ++a) {
+        fine->off[a] = plane_off[a];
+        fine->ratio[a] = ratio[a];
+    }
+    return PT_OK;
 }
 
 extern "C" pt_status probe_grid_read_level(const pt_grid *g, int32_t level, float *out_dev, void *stream) {
@@ -273,9 +315,13 @@ __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewD
     tab[i] = cage_order(g, cell, X);
 }
 
+// Kernel template parameters: W = 64-bit probe addressing, T = two-level hierarchy (L2).
+
 // One view: each wavefront owns one tw x th pixel tile.
-PT_TRACE_KERNEL k_trace_view(GridDev g, ViewDev v, const uint32_t *__restrict__ cage,
-                                                    const uint16_t *__restrict__ rad, Outputs o, int tw, int th) {
+template <bool W, bool T>
+PT_TRACE_KERNEL k_trace_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
+                             const uint32_t *__restrict__ ccage, const uint16_t *__restrict__ rad, Outputs o, int tw,
+                             int th) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int nb = gridDim.x;
     int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
@@ -287,13 +333,13 @@ PT_TRACE_KERNEL k_trace_view(GridDev g, ViewDev v, const uint32_t *__restrict__ 
     float w[3];
     camera_ray(v, x, y, w);
     RayResult r;
-    trace_ray(g, v.pos, w, cage, r);
+    trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
     write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
 }
 
-PT_TRACE_KERNEL k_trace_rays(GridDev g, const float *__restrict__ orig,
-                                                    const float *__restrict__ dirs, int64_t n,
-                                                    const uint16_t *__restrict__ rad, Outputs o) {
+template <bool W, bool T>
+PT_TRACE_KERNEL k_trace_rays(GridDev g, Level2 L2, const float *__restrict__ orig, const float *__restrict__ dirs,
+                             int64_t n, const uint16_t *__restrict__ rad, Outputs o) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float X[3] = {orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
@@ -308,7 +354,7 @@ PT_TRACE_KERNEL k_trace_rays(GridDev g, const float *__restrict__ orig,
     } else {
         float inv = 1.0f / sqrtf(l2);
         float w[3] = {d[0] * inv, d[1] * inv, d[2] * inv};
-        trace_ray(g, X, w, nullptr, r);
+        trace_ray<W, T>(g, L2, X, w, nullptr, nullptr, r);
     }
     write_result(g, rad, r, i, o);
 }
@@ -317,11 +363,11 @@ PT_TRACE_KERNEL k_trace_rays(GridDev g, const float *__restrict__ orig,
 // queue is empty (every wave reaches that exit).
 __global__ void k_reset_counter(int *c) { c[0] = 0; }
 
-PT_TRACE_KERNEL k_trace_persistent(GridDev g, const ViewDev *__restrict__ views, int n_views,
-                                                          const uint32_t *__restrict__ cage, int cells,
-                                                          int total_tiles, int *counter,
-                                                          const uint16_t *__restrict__ rad, Outputs o, int tw,
-                                                          int th) {
+template <bool W, bool T>
+PT_TRACE_KERNEL k_trace_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
+                                   const uint32_t *__restrict__ cage, int cells, const uint32_t *__restrict__ ccage,
+                                   int ccells, int total_tiles, int *counter, const uint16_t *__restrict__ rad,
+                                   Outputs o, int tw, int th) {
     int lane = threadIdx.x & 63;
     for (;;) {
         int tile = 0;
@@ -343,7 +389,8 @@ PT_TRACE_KERNEL k_trace_persistent(GridDev g, const ViewDev *__restrict__ views,
             float w[3];
             camera_ray(v, x, y, w);
             RayResult r;
-            trace_ray(g, v.pos, w, cage + (int64_t)lo * cells, r);
+            trace_ray<W, T>(g, L2, v.pos, w, cage + (int64_t)lo * cells, T ? ccage + (int64_t)lo * ccells : nullptr,
+                            r);
             write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
         }
     }
@@ -393,9 +440,10 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
 }
 
 // Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
-PT_TRACE_KERNEL k_backward_view(GridDev g, ViewDev v, const uint32_t *__restrict__ cage,
-                                                       const float *__restrict__ grad_rgb,
-                                                       float *__restrict__ grad_rad, int tw, int th) {
+template <bool W, bool T>
+PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
+                                const uint32_t *__restrict__ ccage, const float *__restrict__ grad_rgb,
+                                float *__restrict__ grad_rad, int tw, int th) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int nb = gridDim.x;
     int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
@@ -409,7 +457,7 @@ PT_TRACE_KERNEL k_backward_view(GridDev g, ViewDev v, const uint32_t *__restrict
         float w[3];
         camera_ray(v, x, y, w);
         RayResult r;
-        trace_ray(g, v.pos, w, cage, r);
+        trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
         if (r.status == ST_HIT) {
             int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
             float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
@@ -466,6 +514,56 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     d.max_probes = (o.max_probes_per_cell < 1 || o.max_probes_per_cell > 8) ? 8 : o.max_probes_per_cell;
     d.nearest = (o.flags & PT_FLAG_NEAREST) ? 1 : 0;
     return PT_OK;
+}
+
+// Everything a trace launch needs besides views and buffers.
+struct TraceCtx {
+    GridDev d;     // the grid (the fine level of a hierarchy)
+    Level2 L2;     // coarse level (two == true)
+    bool wide, two;
+    int ccells;    // coarse cells
+};
+
+static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
+    memset(&c, 0, sizeof(c));
+    make_griddev(g, opts, c.d);
+    c.two = g->coarse != nullptr;
+    c.wide = g->wide || (opts && (opts->flags & PT_FLAG_WIDE));
+    if (c.two) {
+        make_griddev(g->coarse, opts, c.L2.c);
+        for (int a = 0; a < 3; ++a) {
+            c.L2.off[a] = g->off[a];
+            c.L2.ratio[a] = g->ratio[a];
+        }
+        c.L2.Pf = g->P;
+        c.wide = c.wide || g->coarse->wide;
+        c.ccells = g->coarse->cells;
+    }
+}
+
+// launch the kernel instantiation matching (wide, two)
+#define PT_DISPATCH(c, LAUNCH)                      \
+    do {                                            \
+        if ((c).wide) {                             \
+            if ((c).two) LAUNCH(true, true);        \
+            else LAUNCH(true, false);               \
+        } else {                                    \
+            if ((c).two) LAUNCH(false, true);       \
+            else LAUNCH(false, false);              \
+        }                                           \
+    } while (0)
+
+// cage-order tables of n views (views_dev, or the single view `one`) for both levels
+static void launch_cage_tables(const pt_grid *g, const TraceCtx &c, const ViewDev *views_dev, const ViewDev &one,
+                               int n_views, uint32_t *cage, uint32_t *ccage, hipStream_t s) {
+    int64_t nc = (int64_t)n_views * g->cells;
+    hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, c.d, views_dev, one, n_views,
+                       g->cells, cage);
+    if (c.two) {
+        int64_t ncc = (int64_t)n_views * c.ccells;
+        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(ncc, 256)), dim3(256), 0, s, c.L2.c, views_dev, one,
+                           n_views, c.ccells, ccage);
+    }
 }
 
 static pt_status tile_shape(const pt_trace_opts *opts, int &tw, int &th) {
@@ -552,15 +650,16 @@ static pt_status ensure_device(T *&buf, int64_t &cap, int64_t need, hipStream_t 
     return PT_OK;
 }
 
-static pt_status launch_persistent(pt_grid *g, const GridDev &d, const ViewDev *views_dev, uint32_t *cage,
-                                   int n_views, int tiles, const uint16_t *rad, const Outputs &o, int tw, int th,
-                                   hipStream_t s) {
-    int64_t nc = (int64_t)n_views * g->cells;
-    hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, d, views_dev, ViewDev{}, n_views,
-                       g->cells, cage);
+static pt_status launch_persistent(pt_grid *g, const TraceCtx &c, const ViewDev *views_dev, uint32_t *cage,
+                                   uint32_t *ccage, int n_views, int tiles, const uint16_t *rad, const Outputs &o,
+                                   int tw, int th, hipStream_t s) {
+    launch_cage_tables(g, c, views_dev, ViewDev{}, n_views, cage, ccage, s);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g->counter);
-    hipLaunchKernelGGL(k_trace_persistent, dim3(persistent_blocks(g)), dim3(256), 0, s, d, views_dev, n_views, cage,
-                       g->cells, tiles, g->counter, rad, o, tw, th);
+#define PT_LAUNCH(W, T)                                                                                           \
+    hipLaunchKernelGGL((k_trace_persistent<W, T>), dim3(persistent_blocks(g)), dim3(256), 0, s, c.d, c.L2,       \
+                       views_dev, n_views, cage, g->cells, ccage, c.ccells, tiles, g->counter, rad, o, tw, th)
+    PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }
@@ -570,10 +669,10 @@ static void append_bytes(std::vector<unsigned char> &k, const void *p, size_t n)
     k.insert(k.end(), c, c + n);
 }
 
-static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewDev> &vd, int tiles,
+static pt_status run_graph(pt_grid *g, const TraceCtx &c, const std::vector<ViewDev> &vd, int tiles,
                            const uint16_t *rad, const Outputs &o, int tw, int th, hipStream_t s) {
     std::vector<unsigned char> key;
-    append_bytes(key, &d, sizeof(d));
+    append_bytes(key, &c, sizeof(c));
     append_bytes(key, vd.data(), vd.size() * sizeof(ViewDev));
     append_bytes(key, &rad, sizeof(rad));
     append_bytes(key, &o, sizeof(o));
@@ -595,14 +694,23 @@ static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewD
             HIP_TRY(hipStreamSynchronize(s));
             if (gc.views_dev) HIP_TRY(hipFree(gc.views_dev));
             if (gc.cage) HIP_TRY(hipFree(gc.cage));
+            if (gc.ccage) HIP_TRY(hipFree(gc.ccage));
             gc.views_dev = nullptr;
             gc.cage = nullptr;
+            gc.ccage = nullptr;
             gc.cap = 0;
             if (hipMalloc(&gc.views_dev, sizeof(ViewDev) * n) != hipSuccess)
                 return fail(PT_ERR_OUT_OF_MEMORY, "graph view table allocation");
             if (hipMalloc(&gc.cage, sizeof(uint32_t) * (size_t)n * std::max(1, g->cells)) != hipSuccess)
                 return fail(PT_ERR_OUT_OF_MEMORY, "graph cage table allocation");
             gc.cap = n;
+        }
+        if (c.two) {
+            // the coarse table is sized for the current coarse level (it may be re-attached)
+            if (gc.ccage) HIP_TRY(hipFree(gc.ccage));
+            gc.ccage = nullptr;
+            if (hipMalloc(&gc.ccage, sizeof(uint32_t) * (size_t)n * std::max(1, c.ccells)) != hipSuccess)
+                return fail(PT_ERR_OUT_OF_MEMORY, "graph coarse cage table allocation");
         }
         // the table is baked into this graph: copy it now, outside the capture
         HIP_TRY(hipStreamSynchronize(s));
@@ -611,7 +719,7 @@ static pt_status run_graph(pt_grid *g, const GridDev &d, const std::vector<ViewD
         // stream, which cannot capture); the graph is then launched on the caller's stream
         if (!gc.capture) HIP_TRY(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal));
-        pt_status st = launch_persistent(g, d, gc.views_dev, gc.cage, n, tiles, rad, o, tw, th, gc.capture);
+        pt_status st = launch_persistent(g, c, gc.views_dev, gc.cage, gc.ccage, n, tiles, rad, o, tw, th, gc.capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(gc.capture, &graph);
         if (st != PT_OK) {
@@ -638,24 +746,32 @@ static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_vie
     int tiles;
     st = check_views(views, n_views, tw, th, vd, rays, tiles);
     if (st != PT_OK) return st;
-    GridDev d;
-    make_griddev(g, opts, d);
+    TraceCtx c;
+    make_ctx(g, opts, c);
     uint32_t flags = opts ? opts->flags : 0;
-    if (flags & PT_FLAG_GRAPH) return run_graph(g, d, vd, tiles, rad, o, tw, th, s);
+    if (flags & PT_FLAG_GRAPH) return run_graph(g, c, vd, tiles, rad, o, tw, th, s);
     st = ensure_device(g->cage, g->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
     if (st != PT_OK) return st;
+    if (c.two) {
+        st = ensure_device(g->ccage, g->ccage_cap, (int64_t)n_views * std::max(1, c.ccells), s,
+                           "coarse cage table allocation");
+        if (st != PT_OK) return st;
+    }
     if (flags & PT_FLAG_PERSISTENT) {
         st = upload_views(g, vd, s);
         if (st != PT_OK) return st;
-        return launch_persistent(g, d, g->views_dev, g->cage, n_views, tiles, rad, o, tw, th, s);
+        return launch_persistent(g, c, g->views_dev, g->cage, g->ccage, n_views, tiles, rad, o, tw, th, s);
     }
     for (int i = 0; i < n_views; ++i) {
         int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
         unsigned nb = (unsigned)((vt + 3) / 4);
         uint32_t *cage = g->cage + (int64_t)i * g->cells;
-        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(g->cells, 256)), dim3(256), 0, s, d, nullptr, vd[i], 1,
-                           g->cells, cage);
-        hipLaunchKernelGGL(k_trace_view, dim3(nb), dim3(256), 0, s, d, vd[i], cage, rad, o, tw, th);
+        uint32_t *ccage = c.two ? g->ccage + (int64_t)i * c.ccells : nullptr;
+        launch_cage_tables(g, c, nullptr, vd[i], 1, cage, ccage, s);
+#define PT_LAUNCH(W, T) \
+    hipLaunchKernelGGL((k_trace_view<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], cage, ccage, rad, o, tw, th)
+        PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
     }
     HIP_TRY(hipGetLastError());
     return PT_OK;
@@ -677,11 +793,14 @@ extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: NULL argument");
     if (n < 0) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: n < 0");
     if (n == 0) return PT_OK;
-    GridDev d;
-    make_griddev(g, opts, d);
+    TraceCtx c;
+    make_ctx(g, opts, c);
     Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
-    hipLaunchKernelGGL(k_trace_rays, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, d, origins_dev,
-                       dirs_dev, n, radiance_dev, o);
+#define PT_LAUNCH(W, T)                                                                                        \
+    hipLaunchKernelGGL((k_trace_rays<W, T>), dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c.d, \
+                       c.L2, origins_dev, dirs_dev, n, radiance_dev, o)
+    PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }
@@ -699,20 +818,28 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
     int tiles;
     st = check_views(views_host, n_views, tw, th, vd, rays, tiles);
     if (st != PT_OK) return st;
-    GridDev d;
-    make_griddev(g, opts, d);
+    TraceCtx c;
+    make_ctx(g, opts, c);
     hipStream_t s = (hipStream_t)stream;
     pt_grid *mg = const_cast<pt_grid *>(g);
     st = ensure_device(mg->cage, mg->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
     if (st != PT_OK) return st;
+    if (c.two) {
+        st = ensure_device(mg->ccage, mg->ccage_cap, (int64_t)n_views * std::max(1, c.ccells), s,
+                           "coarse cage table allocation");
+        if (st != PT_OK) return st;
+    }
     for (int i = 0; i < n_views; ++i) {
         int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
         unsigned nb = (unsigned)((vt + 3) / 4);
         uint32_t *cage = mg->cage + (int64_t)i * g->cells;
-        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(g->cells, 256)), dim3(256), 0, s, d, nullptr, vd[i], 1,
-                           g->cells, cage);
-        hipLaunchKernelGGL(k_backward_view, dim3(nb), dim3(256), 0, s, d, vd[i], cage, grad_rgb_dev,
-                           grad_radiance_dev, tw, th);
+        uint32_t *ccage = c.two ? mg->ccage + (int64_t)i * c.ccells : nullptr;
+        launch_cage_tables(g, c, nullptr, vd[i], 1, cage, ccage, s);
+#define PT_LAUNCH(W, T)                                                                                        \
+    hipLaunchKernelGGL((k_backward_view<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], cage, ccage,      \
+                       grad_rgb_dev, grad_radiance_dev, tw, th)
+        PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
     }
     HIP_TRY(hipGetLastError());
     return PT_OK;

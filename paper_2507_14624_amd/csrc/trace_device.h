@@ -55,10 +55,12 @@ __host__ __device__ __forceinline__ int level_offset(int N, int l) {
     return K - (K >> l);
 }
 
-// Texel `idx` (floats from the start of the pyramid); the byte offset fits 32 bits, so the
-// load takes the pyramid base from scalar registers plus one 32-bit lane offset.
-__device__ __forceinline__ float pyr_at(const GridDev &g, uint32_t idx) {
-    return *(const float *)((const char *)g.pyr + (idx << 2));
+// Float `idx` after `bp`.  Narrow addressing: bp is the pyramid base (kernel argument,
+// scalar registers) and idx < 2^30 counts from it, so a load is the scalar base plus one
+// 32-bit lane offset.  Wide addressing (pyramids of 4 GiB and more): bp is the probe's own
+// block, a per-lane 64-bit pointer, and idx < 2 N^2 counts inside the block.
+__device__ __forceinline__ float pyr_at(const float *bp, uint32_t idx) {
+    return *(const float *)((const char *)bp + (idx << 2));
 }
 
 // fire test of a stored distance M against a squared radial distance: M^2 < lim for
@@ -262,13 +264,13 @@ struct Fire {
     float rin2;     // rho^2 at entry
 };
 
-// Hierarchical march of one piece over the probe's MIN pyramid (base = first float of the
-// probe's pyramid block).  Returns true at the first level-0 texel with stored r < max rho.
+// Hierarchical march of one piece over the probe's MIN pyramid (its block starts at float
+// `base` after `bp`).  Returns true at the first level-0 texel with stored r < max rho.
 // (i0, j0): level-0 texel of the ray point at s.ts; rc2: rho^2 there; top: the level the
 // march starts at and never climbs above (at most log2 N - 1, where each quadrant is one
 // texel, so the two children of a texel inside the piece's quadrant are inside it too).
-__device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], const float w[3], const Piece &s,
-                            int i0, int j0, float rc2, int top, Fire &f) {
+__device__ bool march_piece(const GridDev &g, const float *bp, uint32_t base, const float Xp[3], const float w[3],
+                            const Piece &s, int i0, int j0, float rc2, int top, Fire &f) {
     const int N = g.N;
     int l = top;
     int I = i0 >> l, J = j0 >> l;
@@ -289,7 +291,7 @@ __device__ bool march_piece(const GridDev &g, uint32_t base, const float Xp[3], 
         float re2 = rho2_at(Xp, w, texit);
         float m2 = max_pos(rc2, re2);
         // the index stays inside the probe block even if the walk were wrong
-        float M = pyr_at(g, min(off + ((uint32_t)J << g.logN) + (uint32_t)I, last));
+        float M = pyr_at(bp, min(off + ((uint32_t)J << g.logN) + (uint32_t)I, last));
         // coarse levels test conservatively (the min over a parent must not miss a child
         // whose ray span's rho^2 rounds a little above the parent's endpoints)
         float lim = l == 0 ? m2 : m2 * 1.0000153f;
@@ -344,6 +346,7 @@ struct ProbeResult {
 };
 
 // traceOneProbe over [ta, tb] for probe (pi, pj, pk).
+template <bool Wide>
 __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const float X[3], const float w[3],
                             const float iw[3], float ta, float tb, ProbeResult &res) {
     const int N = g.N;
@@ -353,7 +356,8 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
     res.status = ST_MISS;
     res.texel = -1;
     res.eye = false;
-    const uint32_t base = (uint32_t)p * g.stride32;
+    const float *bp = Wide ? g.pyr + (int64_t)p * g.stride : g.pyr;
+    const uint32_t base = Wide ? 0u : (uint32_t)p * g.stride32;
     float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
     if (d2 <= g.eye_eps2) {
         // eye aligned with the probe: every ray point maps to oct(w)
@@ -361,7 +365,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         oct_encode(w[0], w[1], w[2], u, v);
         int i = min(max((int)floorf(__fmaf_rn(u + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
         int j = min(max((int)floorf(__fmaf_rn(v + 1.0f, 0.5f * (float)N, 0.0f)), 0), N - 1);
-        float r = pyr_at(g, base + (uint32_t)(j * N + i));
+        float r = pyr_at(bp, base + (uint32_t)(j * N + i));
         if (r >= ta && r <= tb) {
             res.status = ST_HIT;
             res.texel = j * N + i;
@@ -425,8 +429,8 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
             uint32_t c = (uint32_t)(bj0 >> lv) << g.logN, d = (uint32_t)(bj1 >> lv) << g.logN;
             float lim = max_pos(rs2, rho2_at(Xp, w, hi)) * 1.0000153f;
             // each texel tested on its own: a texel without data (NaN) never fires
-            miss = !(below(pyr_at(g, lev + c + a), lim) | below(pyr_at(g, lev + c + b), lim) |
-                     below(pyr_at(g, lev + d + a), lim) | below(pyr_at(g, lev + d + b), lim));
+            miss = !(below(pyr_at(bp, lev + c + a), lim) | below(pyr_at(bp, lev + c + b), lim) |
+                     below(pyr_at(bp, lev + d + a), lim) | below(pyr_at(bp, lev + d + b), lim));
             // the whole piece fits 2x2 texels of level lv: no coarser level can skip more
             top = min(top, lv);
         }
@@ -434,11 +438,11 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         bool fired = false;
         if (!miss) {
             piece_motion(s);
-            fired = march_piece(g, base, Xp, w, s, i0, j0, rs2, top, f);
+            fired = march_piece(g, bp, base, Xp, w, s, i0, j0, rs2, top, f);
         }
         if (fired) {
             int k = f.j * N + f.i;
-            float r = pyr_at(g, base + (uint32_t)k);
+            float r = pyr_at(bp, base + (uint32_t)k);
             res.texel = k;
             float thr = r * g.tau1;
             // shadow entry: the ray entered the texel behind the stored surface
@@ -447,7 +451,9 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
                 res.status = ST_UNKNOWN;
                 return;
             }
-            uint32_t nb = *(const uint32_t *)((const char *)g.nrm + (((uint32_t)p * (uint32_t)(N * N) + (uint32_t)k) << 2));
+            uint32_t nb = Wide ? g.nrm[(int64_t)p * N * N + k]
+                               : *(const uint32_t *)((const char *)g.nrm +
+                                                     (((uint32_t)p * (uint32_t)(N * N) + (uint32_t)k) << 2));
             float nx, ny, nz;
             oct_decode_unnorm(half_bits((uint16_t)(nb & 0xffffu)), half_bits((uint16_t)(nb >> 16)), nx, ny, nz);
             float nd = __fmaf_rn(nz, w[2], __fmaf_rn(ny, w[1], nx * w[0]));
@@ -512,9 +518,25 @@ __device__ __forceinline__ int cell_index(const GridDev &g, const int cell[3]) {
     return cell[0] + (g.n[0] - 1) * (cell[1] + (g.n[1] - 1) * cell[2]);
 }
 
-// cage: optional per-view table of cage_order() for every cell (same eye for all rays).
-__device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], const uint32_t *__restrict__ cage,
-                          RayResult &out) {
+// Coarse level of a two-level probe hierarchy (the paper shows a hierarchical scene
+// representation without giving its algorithm; this is our reading).  The coarse grid's
+// cell planes are fine planes: coarse plane a of axis x is fine plane off[x] + a ratio[x],
+// so every fine cell (outer, clamped cells too) lies in exactly one coarse cell.  In each
+// fine cell's interval the fine cage is traced first, then the cage of that coarse cell
+// over the same interval; coarse probe p is reported as probe Pf + p.
+struct Level2 {
+    GridDev c;
+    int off[3], ratio[3];
+    int Pf;
+};
+
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// cage / ccage: optional per-view tables of cage_order() for every fine / coarse cell (the
+// eye is the same for all rays of a view).  Two: trace the coarse level of L2 as well.
+template <bool Wide, bool Two>
+__device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], const float w[3],
+                          const uint32_t *__restrict__ cage, const uint32_t *__restrict__ ccage, RayResult &out) {
     out.status = ST_MISS;
     out.probe = -1;
     out.texel = -1;
@@ -540,6 +562,7 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
     bool any_unknown = false, hit = false;
     ProbeResult hp;
     int hc[3] = {0, 0, 0};  // grid coordinates of the HIT probe
+    int hlev = 0;           // its level (1 = coarse)
     float ta = 0.0f;
     const int max_cells = g.n[0] + g.n[1] + g.n[2];
     for (int ci = 0; ci < max_cells; ++ci) {
@@ -553,21 +576,37 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
         }
         float tb = fminf(fminf(fminf(tn[0], tn[1]), tn[2]), tfar);
         uint32_t order = cage ? cage[cell_index(g, cell)] : cage_order(g, cell, X);
-        for (int rk = 0; rk < g.max_probes; ++rk) {
-            int c = (int)(order & 7u);
-            order >>= 3;
-            ProbeResult pr;
-            int pc[3] = {cell[0] + (c & 1), cell[1] + ((c >> 1) & 1), cell[2] + (c >> 2)};
-            trace_probe(g, pc[0], pc[1], pc[2], X, w, iw, ta, tb, pr);
-            if (pr.status == ST_HIT) {
-                hit = true;
-                hp = pr;
-                hc[0] = pc[0];
-                hc[1] = pc[1];
-                hc[2] = pc[2];
-                break;
+        int ccell[3] = {0, 0, 0};
+        uint32_t corder = 0;
+        if (Two) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                ccell[a] = min(max(floor_div(cell[a] - L2.off[a], L2.ratio[a]), 0), L2.c.n[a] - 2);
+            corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_order(L2.c, ccell, X);
+        }
+#pragma unroll 1
+        for (int lev = 0; lev < (Two ? 2 : 1); ++lev) {
+            const GridDev &G = lev ? L2.c : g;
+            uint32_t ord = lev ? corder : order;
+            for (int rk = 0; rk < G.max_probes; ++rk) {
+                int c = (int)(ord & 7u);
+                ord >>= 3;
+                ProbeResult pr;
+                int pc[3] = {(lev ? ccell[0] : cell[0]) + (c & 1), (lev ? ccell[1] : cell[1]) + ((c >> 1) & 1),
+                             (lev ? ccell[2] : cell[2]) + (c >> 2)};
+                trace_probe<Wide>(G, pc[0], pc[1], pc[2], X, w, iw, ta, tb, pr);
+                if (pr.status == ST_HIT) {
+                    hit = true;
+                    hp = pr;
+                    hc[0] = pc[0];
+                    hc[1] = pc[1];
+                    hc[2] = pc[2];
+                    hlev = lev;
+                    break;
+                }
+                if (pr.status == ST_UNKNOWN) any_unknown = true;
             }
-            if (pr.status == ST_UNKNOWN) any_unknown = true;
+            if (hit) break;
         }
         if (hit || !(tb < tfar)) break;
 #pragma unroll
@@ -582,8 +621,9 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
     // Hit distance and point, once per ray after the walk (the lanes of a wavefront reach
     // their HIT at different steps; computing it here keeps the square roots out of the
     // divergent walk).
+    const GridDev &H = (Two && hlev) ? L2.c : g;
     out.status = ST_HIT;
-    out.probe = hc[0] + g.n[0] * (hc[1] + g.n[1] * hc[2]);
+    out.probe = hc[0] + H.n[0] * (hc[1] + H.n[1] * hc[2]) + ((Two && hlev) ? L2.Pf : 0);
     out.texel = hp.texel;
     if (hp.eye) {
         out.t = hp.r;
@@ -594,7 +634,7 @@ __device__ void trace_ray(const GridDev &g, const float X[3], const float w[3], 
     }
     float Xp[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord(g, a, hc[a]);
+    for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord(H, a, hc[a]);
     const float r = hp.r;
     float th;
     if (hp.rin2 >= r * r) {

@@ -19,7 +19,7 @@ class RadianceFit:
         self.grid = grid
         self.views = make_views(views)
         self.target = target_rgb
-        shape = (grid.P, grid.N, grid.N, 3)
+        shape = (grid.P_total, grid.N, grid.N, 3)
         self.master = torch.full(shape, float(init), dtype=torch.float32, device=target_rgb.device,
                                  requires_grad=True)
         self.optim = torch.optim.Adam([self.master], lr=lr)

@@ -80,6 +80,7 @@ class Scene:
     obj_param: np.ndarray  # (K,6) float64
     obj_albedo: np.ndarray  # (K,3)
     seed: int = 0
+    accel: object = None   # optional _Accel (2D grid over x-y listing boxes per cell)
 
     @property
     def n_probes(self) -> int:
@@ -98,7 +99,7 @@ class Scene:
         walls = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(6)])
         objs = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(len(self.obj_type))])
         return Scene(self.dims, self.spacing, self.origin, self.room_max.copy(), walls,
-                     self.obj_type.copy(), self.obj_param.copy(), objs.reshape(-1, 3), seed)
+                     self.obj_type.copy(), self.obj_param.copy(), objs.reshape(-1, 3), seed, self.accel)
 
 
 @dataclass
@@ -157,6 +158,65 @@ def make_scene(seed: int, dims, spacing: float, k_range) -> Scene:
                  np.array(albs, dtype=np.float64).reshape(-1, 3), seed)
 
 
+class _AccelC(ctypes.Structure):
+    _fields_ = [("agx", ctypes.c_int), ("agy", ctypes.c_int), ("acs", ctypes.c_double),
+                ("astart", ctypes.c_void_p), ("aitems", ctypes.c_void_p)]
+
+
+class _Accel:
+    """2D uniform grid over the room's x-y extent listing, per cell, the boxes whose
+    footprint overlaps it (for scenes of thousands of boxes)."""
+
+    def __init__(self, room_max, obj_param, cs: float = 1.0):
+        gx = max(1, int(math.ceil(room_max[0] / cs)))
+        gy = max(1, int(math.ceil(room_max[1] / cs)))
+        lists = [[] for _ in range(gx * gy)]
+        for k, p in enumerate(obj_param):
+            x0 = min(max(int(math.floor((p[0] - p[3]) / cs)), 0), gx - 1)
+            x1 = min(max(int(math.floor((p[0] + p[3]) / cs)), 0), gx - 1)
+            y0 = min(max(int(math.floor((p[1] - p[4]) / cs)), 0), gy - 1)
+            y1 = min(max(int(math.floor((p[1] + p[4]) / cs)), 0), gy - 1)
+            for j in range(y0, y1 + 1):
+                for i in range(x0, x1 + 1):
+                    lists[j * gx + i].append(k)
+        self.start = np.zeros(gx * gy + 1, dtype=np.int32)
+        self.start[1:] = np.cumsum([len(c) for c in lists])
+        self.items = np.array([k for c in lists for k in c], dtype=np.int32)
+        if self.items.size == 0:
+            self.items = np.zeros(1, dtype=np.int32)
+        self.c = _AccelC(gx, gy, float(cs), self.start.ctypes.data, self.items.ctypes.data)
+
+
+def _acc(scene):
+    return ctypes.byref(scene.accel.c) if scene.accel is not None else None
+
+
+def make_city(seed: int, dims, spacing: float, k_range, footprint=(1.0, 4.0), height=(1.0, 12.0)) -> Scene:
+    """A seeded city block: K ~ U{k_range} boxes standing on the ground (footprint sides
+    U[footprint] x U[footprint], height U[height], centres uniform over the ground, no
+    rejection: boxes overlap and may contain probes), albedo U[0.1,0.9]^3, inside a sky
+    box [0, dims*s] whose six inward faces are the walls."""
+    rng = PCG32(seed)
+    dims = tuple(int(d) for d in dims)
+    s = float(spacing)
+    room_max = np.array(dims, dtype=np.float64) * s
+    walls = np.array([[rng.uniform(0.1, 0.9) for _ in range(3)] for _ in range(6)])
+    K = rng.randint(k_range[0], k_range[1])
+    params, albs = [], []
+    for _ in range(K):
+        cx, cy = rng.uniform(0, room_max[0]), rng.uniform(0, room_max[1])
+        hx = 0.5 * rng.uniform(*footprint) * s
+        hy = 0.5 * rng.uniform(*footprint) * s
+        hz = 0.5 * rng.uniform(*height) * s
+        params.append([cx, cy, hz, hx, hy, hz])
+        albs.append([rng.uniform(0.1, 0.9) for _ in range(3)])
+    params = np.array(params, dtype=np.float64).reshape(-1, 6)
+    sc = Scene(dims, s, 0.5 * s, room_max, walls, np.zeros(K, dtype=np.int32), params,
+               np.array(albs, dtype=np.float64).reshape(-1, 3), seed)
+    sc.accel = _Accel(room_max, params, cs=s)
+    return sc
+
+
 def _camera_basis(yaw: float, pitch: float):
     fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
     right = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
@@ -168,7 +228,7 @@ def clearance(scene: Scene, pt) -> float:
     lib = _load()
     pt = np.ascontiguousarray(pt, dtype=np.float64)
     return float(lib.synth_clearance(_dp(scene.room_max), int(len(scene.obj_type)),
-                                     _ip(scene.obj_type), _dp(scene.obj_param), _dp(pt)))
+                                     _ip(scene.obj_type), _dp(scene.obj_param), _dp(pt), _acc(scene)))
 
 
 def _draw_position(rng: PCG32, scene: Scene, min_clear: float):
@@ -242,7 +302,15 @@ class ProbeSet:
         return self.radiance.view(np.float16).astype(np.float32)
 
 
-def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals: str = "geometric") -> ProbeSet:
+def grid_positions(dims, origin: float, spacing: float) -> np.ndarray:
+    """(P,3) float64 positions of a probe grid, p = i + nx*(j + ny*k)."""
+    nx, ny, nz = (int(d) for d in dims)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return float(origin) + float(spacing) * np.stack([i, j, k], axis=-1).reshape(-1, 3).astype(np.float64)
+
+
+def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals: str = "geometric",
+         grid=None) -> ProbeSet:
     """Bake every probe of ``scene`` at N x N texels (centre-ray nearest surface).
 
     normals: "geometric" stores the surface's outward normal; "incoming" stores, as the
@@ -252,8 +320,11 @@ def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals
     if normals not in ("geometric", "incoming"):
         raise ValueError(normals)
     lib = _load()
-    P = scene.n_probes
-    pos = np.ascontiguousarray(scene.probe_positions())
+    # grid = (dims, origin, spacing) of another probe grid in the same scene (default: the
+    # scene's own); a probe inside a box sees D = 0 everywhere
+    gdims, gorg, gsp = grid if grid is not None else (scene.dims, scene.origin, scene.spacing)
+    pos = np.ascontiguousarray(grid_positions(gdims, gorg, gsp))
+    P = len(pos)
     dist = np.empty((P, N, N), dtype=np.float32)
     nrm = np.empty((P, N, N, 2), dtype=np.float32)
     rad = np.empty((P, N, N, 3), dtype=np.float32)
@@ -261,14 +332,14 @@ def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals
     nt = nthreads or min(16, os.cpu_count() or 1)
     lib.synth_bake(_dp(scene.room_max), _dp(scene.wall_albedo), int(len(scene.obj_type)),
                    _ip(scene.obj_type), _dp(scene.obj_param), _dp(scene.obj_albedo), P, _dp(pos), int(N),
-                   _fp(dist), _fp(nrm), _fp(rad), _ip(sid), int(nt))
+                   _fp(dist), _fp(nrm), _fp(rad), _ip(sid), int(nt), _acc(scene))
     if normals == "incoming":
         c = (-1.0 + (2.0 * np.arange(N) + 1.0) / N).astype(np.float32)
         nrm[..., 0] = c[None, None, :]
         nrm[..., 1] = c[None, :, None]
     f32 = lambda v: np.array(v, dtype=np.float32)
     return ProbeSet(
-        dims=tuple(scene.dims), origin=f32([scene.origin] * 3), spacing=f32([scene.spacing] * 3), N=int(N),
+        dims=tuple(int(d) for d in gdims), origin=f32([gorg] * 3), spacing=f32([gsp] * 3), N=int(N),
         levels=int(levels), scene_min=f32([0, 0, 0]), scene_max=f32(scene.room_max),
         distance=dist, normal=nrm.astype(np.float16).view(np.uint16),
         radiance=rad.astype(np.float16).view(np.uint16), extra=dict(surface_id=sid))
@@ -286,7 +357,7 @@ def cast(scene: Scene, origins: np.ndarray, dirs: np.ndarray):
     ids = np.empty(n, dtype=np.int32)
     lib.synth_cast(_dp(scene.room_max), _dp(scene.wall_albedo), int(len(scene.obj_type)), _ip(scene.obj_type),
                    _dp(scene.obj_param), _dp(scene.obj_albedo), ctypes.c_int64(n), _dp(o), _dp(d), _dp(t),
-                   _dp(nn), _dp(alb), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+                   _dp(nn), _dp(alb), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _acc(scene))
     return t, nn, alb, ids
 
 
@@ -302,13 +373,42 @@ CONFIGS = {
                     views=dict(seed=2, n=64, walk=True)),
     "diff": dict(seed=3, dims=(16, 16, 8), spacing=1.0, N=256, levels=6, k_range=(20, 40),
                  target_seed=4, views=dict(seed=103, n=32, width=512, height=512)),
+    # two-level hierarchy over a city block: fine 64x64x16 probes (spacing 1) and coarse
+    # 16x16x4 (spacing 4) whose planes are every 4th fine plane from the second
+    "large": dict(seed=5, dims=(64, 64, 16), spacing=1.0, coarse_dims=(16, 16, 4), plane_off=1, ratio=4,
+                  N=128, levels=5, k_range=(2000, 5000), height=(1.0, 12.0),
+                  views=dict(seed=105, n=8, width=3840, height=2160)),
+    # the same recipe on a 16x16x8 block (test size)
+    "large_small": dict(seed=6, dims=(16, 16, 8), spacing=1.0, coarse_dims=(4, 4, 2), plane_off=1, ratio=4,
+                        N=32, levels=3, k_range=(120, 300), height=(1.0, 6.0),
+                        views=dict(seed=106, n=2, width=160, height=96)),
 }
+
+
+@dataclass
+class TwoLevel:
+    """A fine and a coarse probe set over one scene; coarse plane a of each axis is fine
+    plane plane_off + a * ratio.  Coarse probe p is probe fine.n_probes + p of the pair."""
+    fine: ProbeSet
+    coarse: ProbeSet
+    plane_off: tuple
+    ratio: tuple
+
+    @property
+    def n_probes(self) -> int:
+        return self.fine.n_probes + self.coarse.n_probes
+
+    def radiance(self) -> np.ndarray:
+        """[P_fine + P_coarse][N][N][3] FP16 bits, fine first."""
+        return np.concatenate([self.fine.radiance, self.coarse.radiance])
 
 
 def workload(name: str, N: int | None = None, levels: int | None = None, nthreads: int | None = None,
              n_views: int | None = None, size=None):
     """Build (scene, probes, views) for a named preset; N/levels/n_views/size override for tests."""
     cfg = CONFIGS[name]
+    if "coarse_dims" in cfg:
+        return workload_two_level(name, N, levels, nthreads, n_views, size)
     scene = make_scene(cfg["seed"], cfg["dims"], cfg["spacing"], cfg["k_range"])
     probes = bake(scene, N or cfg["N"], levels or cfg["levels"], nthreads)
     vc = cfg["views"]
@@ -319,6 +419,20 @@ def workload(name: str, N: int | None = None, levels: int | None = None, nthread
         w, h = size if size else (vc["width"], vc["height"])
         views = make_views(scene, vc["seed"], nv, w, h)
     return scene, probes, views
+
+
+def workload_two_level(name: str, N=None, levels=None, nthreads=None, n_views=None, size=None):
+    """(scene, TwoLevel, views) for a two-level preset (city block)."""
+    cfg = CONFIGS[name]
+    scene = make_city(cfg["seed"], cfg["dims"], cfg["spacing"], cfg["k_range"], height=cfg["height"])
+    N, levels = N or cfg["N"], levels or cfg["levels"]
+    fine = bake(scene, N, levels, nthreads)
+    off, r, s = cfg["plane_off"], cfg["ratio"], cfg["spacing"]
+    coarse = bake(scene, N, levels, nthreads, grid=(cfg["coarse_dims"], scene.origin + off * s, r * s))
+    vc = cfg["views"]
+    w, h = size if size else (vc["width"], vc["height"])
+    views = make_views(scene, vc["seed"], n_views or vc["n"], w, h)
+    return scene, TwoLevel(fine, coarse, (off,) * 3, (r,) * 3), views
 
 
 # ---------------------------------------------------------------------------------------------
@@ -357,12 +471,13 @@ def _load():
         D = ctypes.POINTER(ctypes.c_double)
         F = ctypes.POINTER(ctypes.c_float)
         I = ctypes.POINTER(ctypes.c_int32)
+        V = ctypes.c_void_p
         lib.synth_bake.argtypes = [D, D, ctypes.c_int, I, D, D, ctypes.c_int, D, ctypes.c_int, F, F, F, I,
-                                   ctypes.c_int]
+                                   ctypes.c_int, V]
         lib.synth_bake.restype = ctypes.c_int
-        lib.synth_cast.argtypes = [D, D, ctypes.c_int, I, D, D, ctypes.c_int64, D, D, D, D, D, I]
+        lib.synth_cast.argtypes = [D, D, ctypes.c_int, I, D, D, ctypes.c_int64, D, D, D, D, D, I, V]
         lib.synth_cast.restype = ctypes.c_int
-        lib.synth_clearance.argtypes = [D, ctypes.c_int, I, D, D]
+        lib.synth_clearance.argtypes = [D, ctypes.c_int, I, D, D, V]
         lib.synth_clearance.restype = ctypes.c_double
         _lib = lib
     return _lib
