@@ -126,6 +126,56 @@ def differentiable(pt, synth, torch, np, steps=5):
             "loss": [round(x, 6) for x in losses]}
 
 
+def large(pt, synth, torch, np, steps=3):
+    """Two-level city block: fine 64x64x16 + coarse 16x16x4 probes, 128^2 maps (~17 GB of
+    probe data in HBM), 8 views of 3840x2160 in one graph-captured persistent launch;
+    forward and forward + backward."""
+    t0 = time.time()
+    scene, tl, views = synth.workload("large", nthreads=min(16, os.cpu_count() or 1))
+    bake_s = time.time() - t0
+    grid = pt.ProbeGrid.from_two_level(tl)
+    rad = torch.from_numpy(tl.radiance().view(np.float16)).cuda()
+    P, N = tl.n_probes, tl.fine.N
+    dead = float(np.mean([(ps.distance.reshape(ps.n_probes, -1) == 0).all(1).mean() for ps in (tl.fine, tl.coarse)]))
+    n_boxes = len(scene.obj_type)
+    del tl
+    va = pt.make_views(views)
+    rays = pt.n_rays(views)
+    opts = pt.trace_opts(flags=pt.PT_FLAG_GRAPH, tile=(4, 16), start_level=3)
+    out = None
+    res = pt.probe_trace(grid, rad, va, opts, want_t=False, want_status=True, want_hit=False)
+    out = (res["rgb"], None, res["status"], None)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, rad, va, opts, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = out[2].cpu().numpy()
+    hit_frac = float((st == 1).mean())
+    gr = torch.ones((rays, 3), device="cuda")
+    g = torch.zeros((P, N, N, 3), device="cuda")
+    bopts = pt.trace_opts(tile=(4, 16), start_level=3)
+    pt.probe_trace_backward(grid, va, gr, g, bopts)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, rad, va, opts, out=out)
+        pt.probe_trace_backward(grid, va, gr, g, bopts)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / steps
+    return {"workload": f"city block of {n_boxes} boxes; fine 64x64x16 + coarse 16x16x4 probes (coarse planes = every "
+                        f"4th fine plane), 128^2 maps, 5-level pyramids, {P} probes ({dead:.0%} inside buildings, "
+                        f"D = 0); 8 views of 3840x2160", "rays": rays, "hbm_probe_bytes": int(P * N * N * (8 + 4 + 6)),
+            "host_bake_s": round(bake_s, 1), "hit_frac": round(hit_frac, 4),
+            "fwd": {"value": round(rays / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms": round(ms, 3),
+                    "launch": "one graph-captured persistent launch over the 8 views"},
+            "fwd_bwd": {"value": round(rays / (ms_fb * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms": round(ms_fb, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="forward only (for profiling)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable workload")
+    ap.add_argument("--large", action="store_true",
+                    help="also the two-level city block (bakes ~17 GB of probes on the host first)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the tuned options")
     ap.add_argument("--autotune", action="store_true", help="re-run the autotuner and store its choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -248,6 +300,9 @@ def main():
     if not args.no_extras and not args.no_diff:
         print("[bench] differentiable workload", file=sys.stderr, flush=True)
         result["differentiable"] = differentiable(pt, synth, torch, np)
+    if args.large:
+        print("[bench] large two-level workload", file=sys.stderr, flush=True)
+        result["large"] = large(pt, synth, torch, np)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(probes, view)

@@ -584,30 +584,28 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
                 ccell[a] = min(max(floor_div(cell[a] - L2.off[a], L2.ratio[a]), 0), L2.c.n[a] - 2);
             corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_order(L2.c, ccell, X);
         }
-#pragma unroll 1
-        for (int lev = 0; lev < (Two ? 2 : 1); ++lev) {
-            const GridDev &G = lev ? L2.c : g;
-            uint32_t ord = lev ? corder : order;
+        // the cage of one level, closest to the eye first; true on a HIT
+        auto cage_walk = [&](const GridDev &G, const int cl[3], uint32_t ord, int lev) -> bool {
             for (int rk = 0; rk < G.max_probes; ++rk) {
                 int c = (int)(ord & 7u);
                 ord >>= 3;
                 ProbeResult pr;
-                int pc[3] = {(lev ? ccell[0] : cell[0]) + (c & 1), (lev ? ccell[1] : cell[1]) + ((c >> 1) & 1),
-                             (lev ? ccell[2] : cell[2]) + (c >> 2)};
+                int pc[3] = {cl[0] + (c & 1), cl[1] + ((c >> 1) & 1), cl[2] + (c >> 2)};
                 trace_probe<Wide>(G, pc[0], pc[1], pc[2], X, w, iw, ta, tb, pr);
                 if (pr.status == ST_HIT) {
-                    hit = true;
                     hp = pr;
                     hc[0] = pc[0];
                     hc[1] = pc[1];
                     hc[2] = pc[2];
                     hlev = lev;
-                    break;
+                    return true;
                 }
                 if (pr.status == ST_UNKNOWN) any_unknown = true;
             }
-            if (hit) break;
-        }
+            return false;
+        };
+        hit = cage_walk(g, cell, order, 0);
+        if (Two && !hit) hit = cage_walk(L2.c, ccell, corder, 1);
         if (hit || !(tb < tfar)) break;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
