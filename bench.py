@@ -126,6 +126,29 @@ def differentiable(pt, synth, torch, np, steps=5):
             "loss": [round(x, 6) for x in losses]}
 
 
+def bake(pt, synth, torch, np, n_points=4_000_000, steps=5):
+    """Probe maps of the 1080p room (256 probes, 128^2) baked on the GPU from a 4M-point
+    cloud sampled from its surfaces: nearest point per texel, every point against every
+    probe."""
+    scene, probes, views = synth.workload("single", size=(16, 16))
+    pts, col, nrm = synth.sample_points(scene, n_points, 31)
+    pts, col, nrm = (torch.from_numpy(a).cuda() for a in (pts, col, nrm))
+    args = (probes.dims, probes.origin, probes.spacing, probes.N, pts, col, nrm)
+    out = pt.probe_bake_points(*args)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pt.probe_bake_points(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    pairs = probes.n_probes * n_points
+    return {"workload": f"{probes.n_probes} probes x {probes.N}^2 texels from {n_points} points (1080p room)",
+            "ms": round(ms, 3), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 2),
+            "filled_texels": round(float(torch.isfinite(out[0]).float().mean()), 4)}
+
+
 def large(pt, synth, torch, np, steps=3):
     """Two-level city block: fine 64x64x16 + coarse 16x16x4 probes, 128^2 maps (~17 GB of
     probe data in HBM), 8 views of 3840x2160 in one graph-captured persistent launch;
@@ -300,6 +323,9 @@ def main():
     if not args.no_extras and not args.no_diff:
         print("[bench] differentiable workload", file=sys.stderr, flush=True)
         result["differentiable"] = differentiable(pt, synth, torch, np)
+    if not args.no_extras:
+        print("[bench] point-cloud bake", file=sys.stderr, flush=True)
+        result["bake"] = bake(pt, synth, torch, np)
     if args.large:
         print("[bench] large two-level workload", file=sys.stderr, flush=True)
         result["large"] = large(pt, synth, torch, np)

@@ -132,6 +132,31 @@ pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev,
 pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse, const int32_t plane_off[3],
                                 const int32_t ratio[3]);
 
+/* Bake probe maps from a point cloud (Implementation Details, Probe Data Generation):
+ * every point is taken into each probe's frame and projected onto its octahedral map, and
+ * each texel keeps the point nearest to the probe.  The outputs are exactly what
+ * probe_grid_create (distance, normal) and probe_trace (radiance) take.
+ *   desc            probe layout: dims (>= 1 per axis here), origin, spacing, map_res N
+ *                   (mip_levels and the scene box are not used)
+ *   points_dev      [n_points][3] FP32 world positions
+ *   colors_dev      [n_points][3] FP32 colours (stored as FP16, round to nearest even)
+ *   normals_dev     [n_points][3] FP32 surface normals, or NULL: then the "normal" map
+ *                   holds the direction from the probe to the stored point, as the paper
+ *                   literally stores it
+ *   distance_dev    out [P][N][N] FP32 distance to the nearest point; NaN where no point
+ *                   projects (no data: the trace never fires there)
+ *   normal_oct_dev  out [P][N][N][2] FP16 bits, octahedral (u, v); (0, 0) where empty
+ *   radiance_dev    out [P][N][N][3] FP16 bits; 0 where empty
+ * The nearest point is decided in FP32: squared distance ((dx^2 + dy^2) + dz^2) of
+ * p - O with O = origin + k spacing (one rounding), ties to the smaller point index; the
+ * texel of d = p - O is floor((u + 1) N/2) of its octahedral (u, v) with q = d / |d|_1
+ * (correctly rounded), clamped to [0, N-1].  Points at a probe centre are skipped.
+ * Asynchronous on `stream`; the caller keeps the inputs alive until it has run.
+ * Errors: INVALID_ARGUMENT (NULL outputs, bad layout, n_points outside [0, 2^32)), HIP. */
+pt_status probe_bake_points(const pt_grid_desc *desc, const float *points_dev, const float *colors_dev,
+                            const float *normals_dev, int64_t n_points, float *distance_dev,
+                            uint16_t *normal_oct_dev, uint16_t *radiance_dev, void *stream);
+
 /* Free a grid (synchronises the device first).  NULL is ignored. */
 void probe_grid_destroy(pt_grid *grid);
 

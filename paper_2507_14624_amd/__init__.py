@@ -25,7 +25,7 @@ PT_FLAG_NEAREST = 4
 PT_FLAG_WIDE = 8
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
-            "probe_grid_set_coarse",
+            "probe_grid_set_coarse", "probe_bake_points",
             "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_autotune", "pt_last_error")
 
 
@@ -71,11 +71,13 @@ def load_library(path: str = LIB_PATH):
     lib.probe_grid_destroy.restype = None
     lib.probe_grid_read_level.argtypes = [vp, i32, vp, vp]
     lib.probe_grid_set_coarse.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.probe_bake_points.argtypes = [ctypes.POINTER(PtGridDesc), vp, vp, vp, i64, vp, vp, vp, vp]
     lib.probe_trace.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_backward.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_autotune.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, ctypes.POINTER(PtTraceOpts), vp]
-    for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_trace", "probe_trace_rays",
+    for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
+                 "probe_trace", "probe_trace_rays",
                  "probe_trace_backward", "probe_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
@@ -218,6 +220,35 @@ class ProbeGrid:
         out = torch.empty((self.P, n, n), dtype=torch.float32, device=self.device)
         _check(load_library().probe_grid_read_level(self.handle, int(level), _ptr(out), _stream(stream)))
         return out
+
+
+def probe_bake_points(dims, origin, spacing, map_res, points, colors, normals=None, stream=None):
+    """Bake probe maps from a point cloud on the GPU (probe_bake_points).  points, colors,
+    normals: [M,3] float32 (device tensors or arrays; normals None = store the probe-to-point
+    direction).  Returns device tensors distance [P,N,N] float32, normal [P,N,N,2] float16
+    (octahedral u, v), radiance [P,N,N,3] float16."""
+    lib = load_library()
+    dev = torch.device("cuda")
+    pts = _dev_tensor(torch.as_tensor(points, device=dev), torch.float32, "points")
+    col = _dev_tensor(torch.as_tensor(colors, device=dev), torch.float32, "colors")
+    nrm = None if normals is None else _dev_tensor(torch.as_tensor(normals, device=dev), torch.float32, "normals")
+    M = pts.shape[0]
+    _need(pts, 3 * M, "points")
+    _need(col, 3 * M, "colors")
+    _need(nrm, 3 * M, "normals")
+    d = PtGridDesc()
+    d.dims[:] = [int(x) for x in dims]
+    d.origin[:] = [float(x) for x in origin]
+    d.spacing[:] = [float(x) for x in spacing]
+    d.map_res = int(map_res)
+    d.mip_levels = 1
+    P, N = d.dims[0] * d.dims[1] * d.dims[2], d.map_res
+    dist = torch.empty((P, N, N), dtype=torch.float32, device=dev)
+    nrm_out = torch.empty((P, N, N, 2), dtype=torch.float16, device=dev)
+    rad = torch.empty((P, N, N, 3), dtype=torch.float16, device=dev)
+    _check(lib.probe_bake_points(ctypes.byref(d), _ptr(pts), _ptr(col), _ptr(nrm) if nrm is not None else None,
+                                 int(M), _ptr(dist), _ptr(nrm_out), _ptr(rad), _stream(stream)))
+    return dist, nrm_out, rad
 
 
 def _alloc_outputs(rays, device, want_t=True, want_status=True, want_hit=True):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libprobetrace.so")
 SOURCES = [os.path.join(HERE, "csrc", "probetrace.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "trace_device.h"), os.path.join(ROOT, "include", "probetrace.h")]
+HEADERS = [os.path.join(HERE, "csrc", "trace_device.h"), os.path.join(HERE, "csrc", "bake_device.h"),
+           os.path.join(ROOT, "include", "probetrace.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,7 +1,7 @@
 // probetrace: C-ABI library for probe-grid ray tracing on MI355X (gfx950).
 // Kernels: pyramid build, per-view trace, arbitrary-ray trace, persistent multi-view
-// trace over a device tile queue (optionally captured in a hipGraph), and the radiance
-// adjoint.  The contract is in include/probetrace.h.
+// trace over a device tile queue (optionally captured in a hipGraph), the radiance
+// adjoint, and probe baking from a point cloud.  The contract is in include/probetrace.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "bake_device.h"
 #include "probetrace.h"
 #include "trace_device.h"
 
@@ -894,5 +895,105 @@ extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_d
     opts->tile_h = bo.tile_h;
     opts->start_level = bo.start_level;
     opts->flags = bo.flags;
+    return PT_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// probe baking from a point cloud
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBakeThreads)
+    k_bake_points(BakeGrid b, const float *__restrict__ pts, const float *__restrict__ col,
+                  const float *__restrict__ nrm, int64_t M, float *__restrict__ dist, uint32_t *__restrict__ nrm_out,
+                  uint16_t *__restrict__ rad) {
+    __shared__ unsigned long long key[kBakeTile * kBakeTile];
+    const int T = b.tiles, ts = b.ts, N = b.N;
+    const int p = blockIdx.x / (T * T), tt = blockIdx.x % (T * T);
+    const int i0 = (tt % T) * ts, j0 = (tt / T) * ts;
+    const int pi = p % b.n[0], pj = (p / b.n[0]) % b.n[1], pk = p / (b.n[0] * b.n[1]);
+    // probe centre: origin + k spacing, one rounding
+    const float O0 = __fmaf_rn((float)pi, b.spc[0], b.org[0]);
+    const float O1 = __fmaf_rn((float)pj, b.spc[1], b.org[1]);
+    const float O2 = __fmaf_rn((float)pk, b.spc[2], b.org[2]);
+    const float hN = (float)(N / 2);
+    for (int k = threadIdx.x; k < ts * ts; k += blockDim.x) key[k] = ~0ull;
+    __syncthreads();
+    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
+        float dx = pts[3 * m] - O0, dy = pts[3 * m + 1] - O1, dz = pts[3 * m + 2] - O2;
+        float L = (fabsf(dx) + fabsf(dy)) + fabsf(dz);
+        if (!(L > 0.0f)) continue;  // at the probe centre: no direction
+        float u, v;
+        bake_oct(dx, dy, dz, u, v);
+        int i = min(max((int)floorf((u + 1.0f) * hN), 0), N - 1) - i0;
+        int j = min(max((int)floorf((v + 1.0f) * hN), 0), N - 1) - j0;
+        if ((unsigned)i >= (unsigned)ts || (unsigned)j >= (unsigned)ts) continue;  // another tile
+        float r2 = (dx * dx + dy * dy) + dz * dz;
+        unsigned long long k = ((unsigned long long)__float_as_uint(r2) << 32) | (unsigned long long)(uint32_t)m;
+        atomicMin(&key[j * ts + i], k);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ts * ts; k += blockDim.x) {
+        int i = i0 + k % ts, j = j0 + k / ts;
+        int64_t g = (int64_t)p * N * N + (int64_t)j * N + i;
+        unsigned long long kk = key[k];
+        if (kk == ~0ull) {  // no point projects here: no data
+            dist[g] = __uint_as_float(0x7fc00000u);
+            nrm_out[g] = 0u;
+            rad[3 * g] = rad[3 * g + 1] = rad[3 * g + 2] = 0;
+            continue;
+        }
+        int64_t w = (int64_t)(uint32_t)(kk & 0xffffffffull);
+        dist[g] = sqrtf(__uint_as_float((uint32_t)(kk >> 32)));
+        float sx, sy, sz;
+        if (nrm) {
+            sx = nrm[3 * w];
+            sy = nrm[3 * w + 1];
+            sz = nrm[3 * w + 2];
+        } else {  // the probe-to-point direction, as the paper stores it
+            sx = pts[3 * w] - O0;
+            sy = pts[3 * w + 1] - O1;
+            sz = pts[3 * w + 2] - O2;
+        }
+        float u, v;
+        bake_oct(sx, sy, sz, u, v);
+        nrm_out[g] = (uint32_t)__half_as_ushort(__float2half_rn(u)) |
+                     ((uint32_t)__half_as_ushort(__float2half_rn(v)) << 16);
+        rad[3 * g] = __half_as_ushort(__float2half_rn(col[3 * w]));
+        rad[3 * g + 1] = __half_as_ushort(__float2half_rn(col[3 * w + 1]));
+        rad[3 * g + 2] = __half_as_ushort(__float2half_rn(col[3 * w + 2]));
+    }
+}
+
+extern "C" pt_status probe_bake_points(const pt_grid_desc *desc, const float *points_dev, const float *colors_dev,
+                                       const float *normals_dev, int64_t n_points, float *distance_dev,
+                                       uint16_t *normal_oct_dev, uint16_t *radiance_dev, void *stream) {
+    if (!desc || !distance_dev || !normal_oct_dev || !radiance_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: NULL argument");
+    if (n_points < 0 || n_points > (int64_t)UINT32_MAX)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: n_points must be in [0, 2^32)");
+    if (n_points > 0 && (!points_dev || !colors_dev))
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: NULL points or colours");
+    BakeGrid b;
+    memset(&b, 0, sizeof(b));
+    for (int a = 0; a < 3; ++a) {
+        if (desc->dims[a] < 1 || desc->dims[a] > 4096)
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: dims must be in [1, 4096]");
+        if (!std::isfinite(desc->spacing[a]) || !std::isfinite(desc->origin[a]))
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: origin and spacing must be finite");
+        b.n[a] = desc->dims[a];
+        b.org[a] = desc->origin[a];
+        b.spc[a] = desc->spacing[a];
+    }
+    int N = desc->map_res;
+    if (!is_pow2(N) || N < 8 || N > 4096)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: map_res must be a power of two in [8, 4096]");
+    int64_t P = (int64_t)b.n[0] * b.n[1] * b.n[2];
+    b.N = N;
+    b.ts = std::min(N, kBakeTile);
+    b.tiles = N / b.ts;
+    int64_t blocks = P * b.tiles * b.tiles;
+    if (blocks > INT32_MAX) return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: too many probes x tiles");
+    hipLaunchKernelGGL(k_bake_points, dim3((unsigned)blocks), dim3(kBakeThreads), 0, (hipStream_t)stream, b, points_dev,
+                       colors_dev, normals_dev, n_points, distance_dev, (uint32_t *)normal_oct_dev, radiance_dev);
+    HIP_TRY(hipGetLastError());
     return PT_OK;
 }

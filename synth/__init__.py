@@ -345,6 +345,72 @@ def bake(scene: Scene, N: int, levels: int, nthreads: int | None = None, normals
         radiance=rad.astype(np.float16).view(np.uint16), extra=dict(surface_id=sid))
 
 
+def sample_points(scene: Scene, n: int, seed: int):
+    """A seeded synthetic point cloud standing in for the paper's scans (Data Collection):
+    ``n`` points uniform by area over every surface (room walls, box faces, spheres), each
+    with the surface's outward normal and the bake's shaded colour.  Points hidden inside
+    other objects are kept (a projection onto a probe keeps the nearest point per texel, so
+    they never win against the visible surface in front of them).  Random numbers: numpy's
+    PCG64 seeded with ``seed``.  Returns float32 arrays points [n,3], colours [n,3],
+    normals [n,3]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = scene.room_max
+    faces = []  # (centre, half-extent vector u, half-extent vector v, outward normal, albedo)
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for side in (0, 1):
+            ctr = R / 2.0
+            ctr = ctr.copy()
+            ctr[a] = R[a] * side
+            u = np.zeros(3); u[b] = R[b] / 2
+            v = np.zeros(3); v[c] = R[c] / 2
+            nrm = np.zeros(3); nrm[a] = 1.0 if side == 0 else -1.0  # walls face inward
+            faces.append((ctr, u, v, nrm, scene.wall_albedo[2 * a + side]))
+    spheres = []
+    for k, (t, p) in enumerate(zip(scene.obj_type, scene.obj_param)):
+        if t == 0:
+            for a in range(3):
+                b, c = (a + 1) % 3, (a + 2) % 3
+                for sgn in (-1.0, 1.0):
+                    ctr = p[:3].copy()
+                    ctr[a] += sgn * p[3 + a]
+                    u = np.zeros(3); u[b] = p[3 + b]
+                    v = np.zeros(3); v[c] = p[3 + c]
+                    nrm = np.zeros(3); nrm[a] = sgn
+                    faces.append((ctr, u, v, nrm, scene.obj_albedo[k]))
+        else:
+            spheres.append((p[:3], p[3], scene.obj_albedo[k]))
+    area = [4.0 * np.linalg.norm(f[1]) * np.linalg.norm(f[2]) for f in faces] + \
+           [4.0 * math.pi * r * r for _, r, _ in spheres]
+    area = np.array(area)
+    which = rng.choice(len(area), size=n, p=area / area.sum())
+    pts = np.empty((n, 3)); nrm = np.empty((n, 3)); alb = np.empty((n, 3))
+    nf = len(faces)
+    for i, f in enumerate(faces):
+        m = which == i
+        k = int(m.sum())
+        if k:
+            st = rng.uniform(-1.0, 1.0, size=(k, 2))
+            pts[m] = f[0] + st[:, :1] * f[1] + st[:, 1:] * f[2]
+            nrm[m] = f[3]
+            alb[m] = f[4]
+    for j, (c, r, a) in enumerate(spheres):
+        m = which == nf + j
+        k = int(m.sum())
+        if k:
+            d = rng.normal(size=(k, 3))
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            pts[m] = c + r * d
+            nrm[m] = d
+            alb[m] = a
+    light = np.array(_LIGHT) / np.linalg.norm(_LIGHT)
+    col = alb * (0.3 + 0.7 * np.maximum(nrm @ light, 0.0))[:, None]
+    return pts.astype(np.float32), col.astype(np.float32), nrm.astype(np.float32)
+
+
+_LIGHT = (0.3, 0.5, 0.8)  # the bake's light direction (before normalisation)
+
+
 def cast(scene: Scene, origins: np.ndarray, dirs: np.ndarray):
     """Analytic nearest hit: returns t (inf if none), normal (n,3), albedo (n,3), surface id."""
     lib = _load()

@@ -1,0 +1,88 @@
+"""Probe baking from a point cloud on the GPU (probe_bake_points) against the oracle's
+definition (oracle/points.py): the nearest point per texel is an integer decision taken in
+FP32 with the same operations on both sides, so the maps must agree bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from conftest import workload
+from oracle.points import bake_points
+from parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _pt():
+    import paper_2507_14624_amd as pt
+    pt.load_library()
+    return pt
+
+
+def _gpu_bake(probes, N, pts, col, nrm):
+    pt = _pt()
+    d, n, r = pt.probe_bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm)
+    return d.cpu().numpy(), n.cpu().numpy().view(np.uint16), r.cpu().numpy().view(np.uint16)
+
+
+def _same(a, b):
+    return np.array_equal(np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint16),
+                          np.ascontiguousarray(b).view(np.uint32 if b.dtype == np.float32 else np.uint16))
+
+
+@pytest.mark.parametrize("normals", [True, False])
+def test_bake_tiny_room_bit_exact(normals):
+    scene, probes, views = workload("tiny")
+    pts, col, nrm = synth.sample_points(scene, 300000, 21)
+    nrm = nrm if normals else None
+    gd, gn, gr = _gpu_bake(probes, 64, pts, col, nrm)
+    od, on, orad, win = bake_points(probes.dims, probes.origin, probes.spacing, 64, pts, col, nrm)
+    assert np.isnan(od).any() or np.isfinite(od).all()
+    assert np.array_equal(np.isnan(gd), np.isnan(od))
+    assert _same(gd, od) and _same(gn, on) and _same(gr, orad)
+    assert np.isfinite(od).mean() > 0.9
+
+
+def test_bake_room_sampled_probes_and_tiled_maps():
+    # 256 probes at 128^2 (one LDS tile per map) and 256^2 maps (four tiles per map); the
+    # oracle bakes a sample of the probes
+    scene, probes, views = workload("single", size=(64, 64))
+    pts, col, nrm = synth.sample_points(scene, 1_000_000, 22)
+    sel = np.array([0, 17, 100, 133, 200, 255])
+    for N in (128, 256):
+        gd, gn, gr = _gpu_bake(probes, N, pts, col, nrm)
+        od, on, orad, win = bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm, probes=sel)
+        assert _same(gd[sel], od) and _same(gn[sel], on) and _same(gr[sel], orad), N
+
+
+def test_bake_empty_cloud_and_bad_arguments():
+    pt = _pt()
+    scene, probes, views = workload("tiny")
+    z = np.zeros((0, 3), np.float32)
+    d, n, r = pt.probe_bake_points(probes.dims, probes.origin, probes.spacing, 32, z, z)
+    assert torch.isnan(d).all() and (n.view(torch.int16) == 0).all() and (r.view(torch.int16) == 0).all()
+    pts = np.zeros((10, 3), np.float32)
+    with pytest.raises(pt.ProbeTraceError):
+        pt.probe_bake_points(probes.dims, probes.origin, probes.spacing, 48, pts, pts)  # not a power of 2
+    with pytest.raises(pt.ProbeTraceError):
+        pt.probe_bake_points(probes.dims, probes.origin, probes.spacing, 32, pts, pts[:5])  # size mismatch
+
+
+def test_trace_of_a_point_cloud_bake():
+    # bake on the GPU, build the grid from it, trace: parity with the oracle tracing the
+    # oracle's own bake of the same cloud (the maps are identical, so this is the trace
+    # parity on point-cloud data, with its empty texels)
+    pt = _pt()
+    scene, probes, views = workload("tiny")
+    pts, col, nrm = synth.sample_points(scene, 300000, 23)
+    N, L = 64, 4
+    d, n, r = pt.probe_bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm)
+    grid = pt.ProbeGrid(probes.dims, probes.origin, probes.spacing, N, L, probes.scene_min, probes.scene_max, d, n)
+    res = {k: v.cpu().numpy() for k, v in pt.probe_trace(grid, r, [views[0]]).items()}
+    od, on, orad, win = bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm)
+    og = oracle.Grid(probes.dims, probes.origin, probes.spacing, N, L, probes.scene_min, probes.scene_max, od, on, orad)
+    orc = oracle.trace_view(og, views[0].as_tuple())
+    s = compare(res, orc)
+    assert_parity(s, "tiny room 128x128 traced on a 300k-point cloud bake")
+    assert s["hit_frac"] > 0.8
