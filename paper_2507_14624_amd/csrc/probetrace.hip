@@ -440,16 +440,15 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
     }
 }
 
-// Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
+// One wavefront's tile of the adjoint: recompute the trace, then scatter w_tap * grad_rgb
+// into the radiance gradient.  All 64 lanes call it together (the scatter is collective).
 template <bool W, bool T>
-PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
-                                const uint32_t *__restrict__ ccage, const float *__restrict__ grad_rgb,
-                                float *__restrict__ grad_rad, int tw, int th) {
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int nb = gridDim.x;
-    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
-    int tiles_y = (v.H + th - 1) / th;
-    if (tile >= v.tiles_x * tiles_y) return;  // whole wavefronts only
+__device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2, const ViewDev &v, int tile,
+                                              const uint32_t *__restrict__ cage,
+                                              const uint32_t *__restrict__ ccage,
+                                              const float *__restrict__ grad_rgb, float *__restrict__ grad_rad,
+                                              int tw, int th) {
+    int lane = threadIdx.x & 63;
     int x = (tile % v.tiles_x) * tw + lane % tw;
     int y = (tile / v.tiles_x) * th + lane / tw;
     int64_t key[4] = {-1, -1, -1, -1};
@@ -476,6 +475,44 @@ PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t 
         }
     }
     wave_scatter_add(grad_rad, key, val);
+}
+
+// Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
+template <bool W, bool T>
+PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
+                                const uint32_t *__restrict__ ccage, const float *__restrict__ grad_rgb,
+                                float *__restrict__ grad_rad, int tw, int th) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int nb = gridDim.x;
+    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
+    int tiles_y = (v.H + th - 1) / th;
+    if (tile >= v.tiles_x * tiles_y) return;  // whole wavefronts only
+    backward_tile<W, T>(g, L2, v, tile, cage, ccage, grad_rgb, grad_rad, tw, th);
+}
+
+// Persistent adjoint over many views: wavefronts pop tiles of all views from a device
+// counter (views sorted by tile_begin) until the queue is empty.
+template <bool W, bool T>
+PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
+                                      const uint32_t *__restrict__ cage, int cells,
+                                      const uint32_t *__restrict__ ccage, int ccells, int total_tiles,
+                                      int *counter, const float *__restrict__ grad_rgb,
+                                      float *__restrict__ grad_rad, int tw, int th) {
+    int lane = threadIdx.x & 63;
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = atomicAdd(counter, 1);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= total_tiles) return;
+        int lo = 0, hi = n_views - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (views[mid].tile_begin <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        backward_tile<W, T>(g, L2, views[lo], tile - views[lo].tile_begin, cage + (int64_t)lo * cells,
+                            T ? ccage + (int64_t)lo * ccells : nullptr, grad_rgb, grad_rad, tw, th);
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -829,6 +866,23 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
         st = ensure_device(mg->ccage, mg->ccage_cap, (int64_t)n_views * std::max(1, c.ccells), s,
                            "coarse cage table allocation");
         if (st != PT_OK) return st;
+    }
+    uint32_t flags = opts ? opts->flags : 0;
+    if (flags & (PT_FLAG_PERSISTENT | PT_FLAG_GRAPH)) {
+        // one persistent launch over the tiles of all views (the graph flag means the same
+        // here: the adjoint is not captured)
+        st = upload_views(mg, vd, s);
+        if (st != PT_OK) return st;
+        launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, mg->counter);
+#define PT_LAUNCH(W, T)                                                                                          \
+    hipLaunchKernelGGL((k_backward_persistent<W, T>), dim3(persistent_blocks(g)), dim3(256), 0, s, c.d, c.L2,   \
+                       mg->views_dev, n_views, mg->cage, g->cells, mg->ccage, c.ccells, tiles, mg->counter,     \
+                       grad_rgb_dev, grad_radiance_dev, tw, th)
+        PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
+        HIP_TRY(hipGetLastError());
+        return PT_OK;
     }
     for (int i = 0; i < n_views; ++i) {
         int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);

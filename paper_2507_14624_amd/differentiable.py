@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import torch
 
-from . import ProbeTraceFn, make_views
+from . import PT_FLAG_PERSISTENT, ProbeTraceFn, make_views, trace_opts
 
 
 class RadianceFit:
@@ -18,11 +18,18 @@ class RadianceFit:
     def __init__(self, grid, views, target_rgb, init=0.5, lr=1e-2, opts=None):
         self.grid = grid
         self.views = make_views(views)
+        if opts is None and len(self.views) > 1:
+            # many views: one persistent launch over all their tiles, forward and adjoint
+            opts = trace_opts(flags=PT_FLAG_PERSISTENT)
         self.target = target_rgb
         shape = (grid.P_total, grid.N, grid.N, 3)
         self.master = torch.full(shape, float(init), dtype=torch.float32, device=target_rgb.device,
                                  requires_grad=True)
-        self.optim = torch.optim.Adam([self.master], lr=lr)
+        # one fused kernel per step over the 400M-texel master where torch offers it
+        try:
+            self.optim = torch.optim.Adam([self.master], lr=lr, fused=True)
+        except (RuntimeError, TypeError, ValueError):
+            self.optim = torch.optim.Adam([self.master], lr=lr)
         self.opts = opts
 
     def loss(self):

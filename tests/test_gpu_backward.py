@@ -32,9 +32,10 @@ def _setup(name, **kw):
     return pt, scene, probes, views, grid, rad
 
 
-def _check_grad(pt, probes, grid, rad, views, seed=0, nearest=False):
+def _check_grad(pt, probes, grid, rad, views, seed=0, nearest=False, flags=0):
     og = oracle.Grid.from_probes(probes)
-    opts = pt.trace_opts(flags=pt.PT_FLAG_NEAREST) if nearest else None
+    flags |= pt.PT_FLAG_NEAREST if nearest else 0
+    opts = pt.trace_opts(flags=flags) if flags else None
     res = pt.probe_trace(grid, rad, views, opts)
     res = {k: v.cpu().numpy() for k, v in res.items()}
     o_parts, d_parts = [], []
@@ -80,6 +81,14 @@ def test_backward_nearest_texel_radiance():
     # one tap per HIT ray: the gradient of a texel is the sum of its rays' grad_rgb
     pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=2, size=(96, 80))
     _check_grad(pt, probes, grid, rad, views, nearest=True)
+
+
+def test_backward_persistent_launch_over_uneven_views():
+    # the adjoint as one persistent launch over the tiles of all views (the training loop's form)
+    import dataclasses
+    pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=3, size=(96, 80))
+    views = [views[0], dataclasses.replace(views[1], width=53, height=41), dataclasses.replace(views[2], width=120)]
+    _check_grad(pt, probes, grid, rad, views, flags=pt.PT_FLAG_PERSISTENT)
 
 
 def test_backward_accumulates():

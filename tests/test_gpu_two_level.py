@@ -122,6 +122,10 @@ def test_two_level_backward_matches_oracle_vjp():
     gg = torch.zeros((tl.n_probes, tl.fine.N, tl.fine.N, 3), device="cuda")
     pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gg)
     got = gg.cpu().numpy().astype(np.float64)
+    # the persistent adjoint over both views gives the same sums up to atomic order
+    gp = torch.zeros_like(gg)
+    pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gp, pt.trace_opts(flags=pt.PT_FLAG_PERSISTENT))
+    torch.testing.assert_close(gp, gg, rtol=1e-5, atol=1e-6)
     ref = oracle.vjp((og, cg), orc, g.astype(np.float64))
     wabs = oracle.vjp((og, cg), orc, np.abs(g).astype(np.float64))
     unit = dict(orc)
