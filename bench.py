@@ -34,7 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_fwd_1080p_traffic.md")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("probetrace.hip", "trace_device.h"):
+    for f in ("probetrace.hip", "trace_device.h", "bake_device.h"):
         with open(os.path.join(ROOT, "paper_2507_14624_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -263,7 +263,7 @@ def main():
     achieved_gbs = ab["total_bytes"] / (ms * 1e-3) / 1e9
     achieved_tflops = ab["total_flops"] / (ms * 1e-3) / 1e12
     traffic = measured_traffic()
-    kernel = "k_trace_persistent" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view"
+    kernel = "k_trace_persistent<false, false>" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view<false, false>"
     result = {
         "metric": "Mrays/s probe trace (fwd, fwd+bwd) at 1080p; HBM GB/s vs peak; batched vs plain",
         "value": round(value, 3),
