@@ -387,28 +387,39 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
     float c1 = clamp_nn(cut[2], lo01, hi01);
     float c2 = max_nn(g.inf, hi01, cut[2]);
     int nc = (c0 < INFINITY) + (c1 < INFINITY) + (c2 < INFINITY);
+    // position scale of the L forms (|Xp|_1 + |t w|_1 bounded by 2 tb) and the trim
+    // threshold on L near the probe centre
+    const float thr = (((fabsf(Xp[0]) + fabsf(Xp[1])) + fabsf(Xp[2])) + 2.0f * tb) * 0x1p-12f;
     float lo = ta;
     for (int sgi = 0; sgi <= nc; ++sgi) {
         float hi = sgi == nc ? tb : (sgi == 0 ? c0 : (sgi == 1 ? c1 : c2));
         Piece s;
         piece_setup(s, Xp, w, lo, hi, N);
-        // the march starts from the texel of the start point; if the piece starts at the
-        // probe origin (L = 0 there), from the texel of its midpoint
-        float Ls0 = __fmaf_rn(lo, s.L1, s.L0);
+        // Near the probe centre (L, the L1 norm of the ray point in the piece's octant,
+        // below 2^-12 of the position scale) the projected coordinates are rounding noise:
+        // that stretch of the piece is trimmed off, and the whole piece when nothing is
+        // left.  Nothing could fire on it unless a stored distance were below 2^-12 of the
+        // scale (rho <= L there).  A ray that passes a probe at a distance keeps its pieces.
+        bool miss = false;
         float xs, ys, Ls, xe, ye, Le;
-        piece_xy(s, Xp, w, Ls0 > 0.0f ? lo : 0.5f * (s.ts + s.te), N, xs, ys, Ls);
+        piece_xy(s, Xp, w, lo, N, xs, ys, Ls);
         piece_xy(s, Xp, w, hi, N, xe, ye, Le);
-        if (!(Ls > 0.0f)) {
-            xs = (float)s.ilo;
-            ys = (float)s.jlo;
+        if (!(Ls >= thr) | !(Le >= thr)) {
+            float tz = (thr - s.L0) / s.L1;  // where L reaches thr (+-inf or NaN if L is constant)
+            if (s.L1 > 0.0f) s.ts = fmaxf(lo, tz);
+            if (s.L1 < 0.0f) s.te = fminf(hi, tz);
+            piece_xy(s, Xp, w, s.ts, N, xs, ys, Ls);
+            piece_xy(s, Xp, w, s.te, N, xe, ye, Le);
+            float hthr = 0.5f * thr;
+            miss = !(s.ts <= s.te) | !(Ls >= hthr) | !(Le >= hthr);
         }
+        // the march starts from the texel of the (trimmed) start point
         int fxs = (int)floorf(xs), fys = (int)floorf(ys);
         int i0 = min(max(fxs, s.ilo), s.ihi);
         int j0 = min(max(fys, s.jlo), s.jhi);
-        float rs2 = rho2_at(Xp, w, lo);
-        bool miss = false;
+        float rs2 = rho2_at(Xp, w, s.ts);
         int top = g.top;
-        if (Ls0 > 0.0f && Le > 0.0f) {
+        if (!miss) {
             int fxe = (int)floorf(xe), fye = (int)floorf(ye);
             // O(1) MISS test of the whole piece: its projection is a straight segment, so the
             // texels it crosses lie in the box spanned by its end texels (widened by one texel
@@ -427,7 +438,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
             uint32_t lev = base + (uint32_t)level_offset(N, lv);
             uint32_t a = (uint32_t)(bi0 >> lv), b = (uint32_t)(bi1 >> lv);
             uint32_t c = (uint32_t)(bj0 >> lv) << g.logN, d = (uint32_t)(bj1 >> lv) << g.logN;
-            float lim = max_pos(rs2, rho2_at(Xp, w, hi)) * 1.0000153f;
+            float lim = max_pos(rs2, rho2_at(Xp, w, s.te)) * 1.0000153f;
             // each texel tested on its own: a texel without data (NaN) never fires
             miss = !(below(pyr_at(bp, lev + c + a), lim) | below(pyr_at(bp, lev + c + b), lim) |
                      below(pyr_at(bp, lev + d + a), lim) | below(pyr_at(bp, lev + d + b), lim));

@@ -243,3 +243,15 @@ def test_two_probe_limit_is_a_subset(tiny):
     assert np.array_equal(r2["texel"][ok], r8["texel"][ok])
     assert np.all(r8["rank"][ok] % 8 < 2)
     assert (r8["status"] == oracle.HIT).sum() >= h2.sum()
+
+
+def test_degenerate_rays_give_valid_hits(tiny, single_small):
+    # axis-aligned rays, rays through probe centres and along cell planes: every HIT point
+    # lies in its texel at a radial distance in [r, r (1 + tau)]
+    from degenerate import degenerate_rays, hit_is_valid
+    for scene, probes, views in (tiny, single_small):
+        o, d, tag = degenerate_rays(scene, probes)
+        r = oracle.trace(oracle.Grid.from_probes(probes), o.astype(np.float64), d.astype(np.float64))
+        hit = np.stack([r["probe"], r["texel"]], 1)
+        assert hit_is_valid(probes, o, d.astype(np.float64), r["status"], hit, r["t"], 8.0 / probes.N).all()
+        assert (r["status"] == oracle.HIT).mean() > 0.95
