@@ -263,7 +263,7 @@ def main():
     achieved_gbs = ab["total_bytes"] / (ms * 1e-3) / 1e9
     achieved_tflops = ab["total_flops"] / (ms * 1e-3) / 1e12
     traffic = measured_traffic()
-    kernel = "k_trace_persistent<false, false>" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view<false, false>"
+    kernel = "k_trace_persistent<false, 0>" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view<false, 0>"
     result = {
         "metric": "Mrays/s probe trace (fwd, fwd+bwd) at 1080p; HBM GB/s vs peak; batched vs plain",
         "value": round(value, 3),

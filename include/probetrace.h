@@ -60,9 +60,13 @@ typedef enum { PT_MISS = 0, PT_HIT = 1, PT_UNKNOWN = 2 } pt_ray_status;
 
 typedef struct pt_grid pt_grid; /* opaque: the probe geometry resident on one device */
 
-/* Uniform probe grid (Figure 3(a): probes at the vertices of a uniform 3D grid). */
+/* Uniform probe grid (Figure 3(a): probes at the vertices of a uniform 3D grid).  A layout
+ * of fewer than 8 probes (Ray Trace Using Multiple Probes, less than 8 probes) has no grid
+ * iterator: every ray tries all its probes, closest to the eye first (ties by probe index),
+ * over its whole length. */
 typedef struct {
-    int32_t dims[3];      /* probes per axis, each >= 2 */
+    int32_t dims[3];      /* probes per axis: each >= 2 for 8 or more probes; >= 1 (with
+                             fewer than 8 probes in all) for the small layouts above */
     float origin[3];      /* position of probe (0,0,0) */
     float spacing[3];     /* > 0; probe (i,j,k) at origin + (i,j,k)*spacing */
     int32_t map_res;      /* N: power of two, 8 <= N <= 4096 */
@@ -88,7 +92,8 @@ typedef struct {
     float eye_eps_rel;            /* eye at a probe when |X - O| <= eye_eps_rel * min spacing;
                                      <= 0 selects 1e-6 */
     float background[3];          /* rgb written for rays that are not HIT */
-    int32_t max_probes_per_cell;  /* probes tried per cell, 1..8; <= 0 selects 8 */
+    int32_t max_probes_per_cell;  /* probes tried per cell, 1..8; <= 0 selects 8 (all of
+                                     them in a layout of fewer than 8 probes) */
     int32_t tile_w, tile_h;       /* pixels per wavefront tile, tile_w * tile_h = 64; 0 = 8x8 */
     int32_t start_level;          /* pyramid level the march starts at; < 0 = coarsest */
     uint32_t flags;               /* PT_FLAG_* */
@@ -113,8 +118,8 @@ void pt_trace_opts_default(pt_trace_opts *opts);
  *   normal_oct_dev  [P][N][N][2] FP16 bits: octahedral (u, v) of the stored normal
  * The library copies both into its own layout and builds the MIN pyramid on `stream`; the
  * caller keeps its arrays alive until `stream` has passed this call.  *out receives the
- * grid (NULL on failure).  Errors: INVALID_ARGUMENT (bad desc or NULL pointer),
- * OUT_OF_MEMORY, HIP. */
+ * grid (NULL on failure).  Errors: INVALID_ARGUMENT (bad desc or NULL pointer; 8 or more
+ * probes with an axis of 1), OUT_OF_MEMORY, HIP. */
 pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev, const uint16_t *normal_oct_dev,
                             void *stream, pt_grid **out);
 
@@ -128,7 +133,8 @@ pt_status probe_grid_create(const pt_grid_desc *desc, const float *distance_dev,
  * is probe P_fine + p everywhere: in hit_dev, in radiance_dev ([P_fine + P_coarse][N][N][3],
  * fine first) and in grad_radiance_dev.  Both levels need the same map resolution N.  The
  * caller keeps `coarse` alive while attached; coarse = NULL detaches.  Errors:
- * INVALID_ARGUMENT (NULL fine grid, mismatched planes or N, coarse itself two-level). */
+ * INVALID_ARGUMENT (NULL fine grid, mismatched planes or N, coarse itself two-level, a
+ * level of fewer than 8 probes). */
 pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse, const int32_t plane_off[3],
                                 const int32_t ratio[3]);
 

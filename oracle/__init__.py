@@ -120,6 +120,9 @@ class Grid:
     def __init__(self, dims, origin, spacing, N, levels, scene_min, scene_max, distance, normal_bits,
                  radiance):
         self.dims = tuple(int(d) for d in dims)
+        if min(self.dims) < 1 or (np.prod(self.dims) >= 8 and min(self.dims) < 2):
+            # 8 or more probes form a grid (every axis >= 2); fewer are traced all together
+            raise ValueError(f"probe layout {self.dims}: 8 or more probes need at least 2 per axis")
         self.N = int(N)
         self.levels = int(levels)
         self.origin = np.asarray(origin, dtype=np.float64)

@@ -603,22 +603,49 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
 /* ------------------------------------------------------------------------------------
  * One camera ray: grid iterator over cells, closest-first cage probes, fall-through.
  * ------------------------------------------------------------------------------------ */
-/* the 8 corner probes of a cell, closest to the eye first, ties by corner code */
-static void cage_sort(const grid_t *g, const int cell[3], const double X[3], int code[8], double dd[8]) {
-    for (int c = 0; c < 8; ++c) {
-        int ci = cell[0] + (c & 1), cj = cell[1] + ((c >> 1) & 1), ck = cell[2] + (c >> 2);
+/* Fewer than 8 probes (Methodology, Ray Trace Using Multiple Probes: less than 8 probes):
+ * no grid iterator; every probe, closest to the eye first, over the whole ray. */
+static int few_probes(const grid_t *g) { return g->dims[0] * g->dims[1] * g->dims[2] < 8; }
+
+/* last cell index per axis: dims - 2 for a grid, 0 (one cell, no interior plane) for a
+ * scene of fewer than 8 probes */
+static int cell_max(const grid_t *g, int a) { return few_probes(g) ? 0 : g->dims[a] - 2; }
+
+/* probe of cage entry c of a cell: corner code c = dx + 2 dy + 4 dz of the cell, or, with
+ * fewer than 8 probes, probe index c itself */
+static int cage_probe(const grid_t *g, const int cell[3], int c, int pc[3]) {
+    if (few_probes(g)) {
+        pc[0] = c % g->dims[0];
+        pc[1] = (c / g->dims[0]) % g->dims[1];
+        pc[2] = c / (g->dims[0] * g->dims[1]);
+        return c;
+    }
+    pc[0] = cell[0] + (c & 1);
+    pc[1] = cell[1] + ((c >> 1) & 1);
+    pc[2] = cell[2] + (c >> 2);
+    return pc[0] + g->dims[0] * (pc[1] + g->dims[1] * pc[2]);
+}
+
+/* the cage probes of a cell, closest to the eye first, ties by corner code (probe index);
+ * returns how many there are (8, or the number of probes when there are fewer) */
+static int cage_sort(const grid_t *g, const int cell[3], const double X[3], int code[8], double dd[8]) {
+    int n = few_probes(g) ? g->dims[0] * g->dims[1] * g->dims[2] : 8;
+    for (int c = 0; c < n; ++c) {
+        int pc[3];
+        cage_probe(g, cell, c, pc);
         double d2 = 0;
-        double O[3] = {g->origin[0] + ci * g->spacing[0], g->origin[1] + cj * g->spacing[1],
-                       g->origin[2] + ck * g->spacing[2]};
+        double O[3] = {g->origin[0] + pc[0] * g->spacing[0], g->origin[1] + pc[1] * g->spacing[1],
+                       g->origin[2] + pc[2] * g->spacing[2]};
         for (int a = 0; a < 3; ++a) d2 += (O[a] - X[a]) * (O[a] - X[a]);
         code[c] = c;
         dd[c] = sqrt(d2);
     }
-    for (int a = 1; a < 8; ++a) /* insertion sort, stable: ties keep corner-code order */
+    for (int a = 1; a < n; ++a) /* insertion sort, stable: ties keep corner-code order */
         for (int b = a; b > 0 && dd[b] < dd[b - 1]; --b) {
             double td = dd[b]; dd[b] = dd[b - 1]; dd[b - 1] = td;
             int tc = code[b]; code[b] = code[b - 1]; code[b - 1] = tc;
         }
+    return n;
 }
 
 static inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
@@ -649,9 +676,9 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
     int cell[3];
     for (int a = 0; a < 3; ++a) {
         double q = (X[a] - g->origin[a]) / g->spacing[a];
-        cell[a] = clampi((int)floor(q), 0, g->dims[a] - 2);
+        cell[a] = clampi((int)floor(q), 0, cell_max(g, a));
         double c = floor(q + 0.5);
-        if (c >= 1 && c <= g->dims[a] - 2) decide(&mc, q - c, 4.0 * (fabs(X[a]) + fabs(g->origin[a])), MG_CELL);
+        if (c >= 1 && c <= cell_max(g, a)) decide(&mc, q - c, 4.0 * (fabs(X[a]) + fabs(g->origin[a])), MG_CELL);
     }
     double ta = 0.0, Eta = 0.0;
     int mp = o->max_probes_per_cell < 1 || o->max_probes_per_cell > 8 ? 8 : o->max_probes_per_cell;
@@ -663,7 +690,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
         for (int a = 0; a < 3; ++a) {
             tn[a] = INFINITY; En[a] = 0;
             int pidx = -1;
-            if (w[a] > 0 && cell[a] + 1 <= g->dims[a] - 2) pidx = cell[a] + 1;
+            if (w[a] > 0 && cell[a] + 1 <= cell_max(g, a)) pidx = cell[a] + 1;
             else if (w[a] < 0 && cell[a] >= 1) pidx = cell[a];
             if (pidx >= 0) {
                 double plane = g->origin[a] + pidx * g->spacing[a];
@@ -684,7 +711,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
         int ccell[3] = {0, 0, 0};
         if (cg)
             for (int a = 0; a < 3; ++a)
-                ccell[a] = clampi(floordiv(cell[a] - L2->plane_off[a], L2->ratio[a]), 0, cg->dims[a] - 2);
+                ccell[a] = clampi(floordiv(cell[a] - L2->plane_off[a], L2->ratio[a]), 0, cell_max(cg, a));
         const int Pf = g->dims[0] * g->dims[1] * g->dims[2];
         for (int lev = 0; lev < (cg ? 2 : 1); ++lev) {
             const grid_t *G = lev == 0 ? g : cg;
@@ -692,11 +719,11 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
             /* cage: the 8 corner probes, closest to the eye first, ties by corner code */
             int code[8];
             double dd[8];
-            cage_sort(G, cl, X, code, dd);
-            for (int rk = 0; rk < mp; ++rk) {
-                int c = code[rk];
-                int p = (cl[0] + (c & 1)) +
-                        G->dims[0] * ((cl[1] + ((c >> 1) & 1)) + G->dims[1] * (cl[2] + (c >> 2)));
+            int ncage = cage_sort(G, cl, X, code, dd);
+            int mpc = mp < ncage ? mp : ncage;
+            for (int rk = 0; rk < mpc; ++rk) {
+                int pc[3];
+                int p = cage_probe(G, cl, code[rk], pc);
                 presult_t pr;
                 trace_one_probe(G, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
                 ++n_probe;
@@ -707,7 +734,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
                 if (pr.status == ST_HIT) {
                     /* the order only mattered if the resolving probe nearly tied with a neighbour */
                     double cs = 8.0 * (dd[rk] + 4.0 * G->spacing[0]);
-                    if (rk + 1 < mp) decide(&mc, dd[rk + 1] - dd[rk], cs, MG_CAGE);
+                    if (rk + 1 < mpc) decide(&mc, dd[rk + 1] - dd[rk], cs, MG_CAGE);
                     if (rk > 0) decide(&mc, dd[rk] - dd[rk - 1], cs, MG_CAGE);
                     out->status[ri] = ST_HIT;
                     out->t[ri] = pr.t;

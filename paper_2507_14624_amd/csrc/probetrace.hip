@@ -148,8 +148,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     if (!desc || !distance_dev || !normal_oct_dev || !out)
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: NULL argument");
     for (int a = 0; a < 3; ++a) {
-        if (desc->dims[a] < 2 || desc->dims[a] > 4096)
-            return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: dims must be in [2, 4096]");
+        if (desc->dims[a] < 1 || desc->dims[a] > 4096)
+            return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: dims must be in [1, 4096]");
         if (!(desc->spacing[a] > 0.0f) || !std::isfinite(desc->spacing[a]) || !std::isfinite(desc->origin[a]))
             return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: spacing must be finite and > 0");
         if (!(desc->scene_max[a] > desc->scene_min[a]))
@@ -162,6 +162,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: mip_levels must satisfy N >> (L-1) >= 2");
     int64_t P = (int64_t)desc->dims[0] * desc->dims[1] * desc->dims[2];
     if (P > (1 << 24)) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: too many probes");
+    if (P >= 8 && std::min(desc->dims[0], std::min(desc->dims[1], desc->dims[2])) < 2)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_create: 8 or more probes need at least 2 per axis");
 
     pt_grid *g = new (std::nothrow) pt_grid();
     if (!g) return fail(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: host allocation");
@@ -175,7 +177,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
     g->wide = P * g->stride * (int64_t)sizeof(float) > (int64_t)UINT32_MAX;
     g->Lc = 0;
     while ((2 << g->Lc) <= N) ++g->Lc;  // levels down to 2x2 (log2 N of them)
-    g->cells = (desc->dims[0] - 1) * (desc->dims[1] - 1) * (desc->dims[2] - 1);
+    // fewer than 8 probes: one cell (no grid iterator)
+    g->cells = P < 8 ? 1 : (desc->dims[0] - 1) * (desc->dims[1] - 1) * (desc->dims[2] - 1);
     hipStream_t s = (hipStream_t)stream;
     auto cleanup = [&](pt_status st, const std::string &m) {
         probe_grid_destroy(g);
@@ -236,6 +239,8 @@ extern "C" pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse,
     if (!plane_off || !ratio) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: NULL plane map");
     if (coarse->N != fine->N)
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: both levels need the same map resolution");
+    if (fine->P < 8 || coarse->P < 8)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: both levels must be grids of 8 or more probes");
     if (coarse->device != fine->device)
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_coarse: levels on different devices");
     for (int a = 0; a < 3; ++a) {
@@ -311,15 +316,16 @@ __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewD
     if (i >= (int64_t)n_views * cells) return;
     int v = (int)(i / cells), c = (int)(i % cells);
     const float *X = views ? views[v].pos : single.pos;
-    int nx = g.n[0] - 1, ny = g.n[1] - 1;
+    int nx = g.cmax[0] + 1, ny = g.cmax[1] + 1;
     int cell[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
-    tab[i] = cage_order(g, cell, X);
+    tab[i] = g.few ? cage_order<true>(g, cell, X) : cage_order<false>(g, cell, X);
 }
 
-// Kernel template parameters: W = 64-bit probe addressing, T = two-level hierarchy (L2).
+// Kernel template parameters: W = 64-bit probe addressing, T = layout (kGrid, kTwoLevel:
+// the hierarchy of L2, kFew: fewer than 8 probes).
 
 // One view: each wavefront owns one tw x th pixel tile.
-template <bool W, bool T>
+template <bool W, int T>
 PT_TRACE_KERNEL k_trace_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
                              const uint32_t *__restrict__ ccage, const uint16_t *__restrict__ rad, Outputs o, int tw,
                              int th) {
@@ -338,7 +344,7 @@ PT_TRACE_KERNEL k_trace_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__
     write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
 }
 
-template <bool W, bool T>
+template <bool W, int T>
 PT_TRACE_KERNEL k_trace_rays(GridDev g, Level2 L2, const float *__restrict__ orig, const float *__restrict__ dirs,
                              int64_t n, const uint16_t *__restrict__ rad, Outputs o) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -364,7 +370,7 @@ PT_TRACE_KERNEL k_trace_rays(GridDev g, Level2 L2, const float *__restrict__ ori
 // queue is empty (every wave reaches that exit).
 __global__ void k_reset_counter(int *c) { c[0] = 0; }
 
-template <bool W, bool T>
+template <bool W, int T>
 PT_TRACE_KERNEL k_trace_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
                                    const uint32_t *__restrict__ cage, int cells, const uint32_t *__restrict__ ccage,
                                    int ccells, int total_tiles, int *counter, const uint16_t *__restrict__ rad,
@@ -390,7 +396,7 @@ PT_TRACE_KERNEL k_trace_persistent(GridDev g, Level2 L2, const ViewDev *__restri
             float w[3];
             camera_ray(v, x, y, w);
             RayResult r;
-            trace_ray<W, T>(g, L2, v.pos, w, cage + (int64_t)lo * cells, T ? ccage + (int64_t)lo * ccells : nullptr,
+            trace_ray<W, T>(g, L2, v.pos, w, cage + (int64_t)lo * cells, T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr,
                             r);
             write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
         }
@@ -442,7 +448,7 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
 
 // One wavefront's tile of the adjoint: recompute the trace, then scatter w_tap * grad_rgb
 // into the radiance gradient.  All 64 lanes call it together (the scatter is collective).
-template <bool W, bool T>
+template <bool W, int T>
 __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2, const ViewDev &v, int tile,
                                               const uint32_t *__restrict__ cage,
                                               const uint32_t *__restrict__ ccage,
@@ -478,7 +484,7 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
 }
 
 // Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
-template <bool W, bool T>
+template <bool W, int T>
 PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
                                 const uint32_t *__restrict__ ccage, const float *__restrict__ grad_rgb,
                                 float *__restrict__ grad_rad, int tw, int th) {
@@ -492,7 +498,7 @@ PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t 
 
 // Persistent adjoint over many views: wavefronts pop tiles of all views from a device
 // counter (views sorted by tile_begin) until the queue is empty.
-template <bool W, bool T>
+template <bool W, int T>
 PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
                                       const uint32_t *__restrict__ cage, int cells,
                                       const uint32_t *__restrict__ ccage, int ccells, int total_tiles,
@@ -511,7 +517,7 @@ PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__res
             else hi = mid - 1;
         }
         backward_tile<W, T>(g, L2, views[lo], tile - views[lo].tile_begin, cage + (int64_t)lo * cells,
-                            T ? ccage + (int64_t)lo * ccells : nullptr, grad_rgb, grad_rad, tw, th);
+                            T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr, grad_rgb, grad_rad, tw, th);
     }
 }
 
@@ -550,6 +556,9 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     float ms = std::min(g->desc.spacing[0], std::min(g->desc.spacing[1], g->desc.spacing[2]));
     d.eye_eps2 = (eps * ms) * (eps * ms);
     d.max_probes = (o.max_probes_per_cell < 1 || o.max_probes_per_cell > 8) ? 8 : o.max_probes_per_cell;
+    d.few = g->P < 8 ? 1 : 0;
+    for (int a = 0; a < 3; ++a) d.cmax[a] = d.few ? 0 : g->desc.dims[a] - 2;
+    if (d.few) d.max_probes = std::min(d.max_probes, g->P);
     d.nearest = (o.flags & PT_FLAG_NEAREST) ? 1 : 0;
     return PT_OK;
 }
@@ -579,16 +588,19 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
     }
 }
 
-// launch the kernel instantiation matching (wide, two)
-#define PT_DISPATCH(c, LAUNCH)                      \
-    do {                                            \
-        if ((c).wide) {                             \
-            if ((c).two) LAUNCH(true, true);        \
-            else LAUNCH(true, false);               \
-        } else {                                    \
-            if ((c).two) LAUNCH(false, true);       \
-            else LAUNCH(false, false);              \
-        }                                           \
+// launch the kernel instantiation matching (wide, layout); a layout of fewer than 8 probes
+// always fits the narrow addressing
+#define PT_DISPATCH(c, LAUNCH)                              \
+    do {                                                    \
+        if ((c).d.few) {                                    \
+            LAUNCH(false, kFew);                            \
+        } else if ((c).wide) {                              \
+            if ((c).two) LAUNCH(true, kTwoLevel);           \
+            else LAUNCH(true, kGrid);                       \
+        } else {                                            \
+            if ((c).two) LAUNCH(false, kTwoLevel);          \
+            else LAUNCH(false, kGrid);                      \
+        }                                                   \
     } while (0)
 
 // cage-order tables of n views (views_dev, or the single view `one`) for both levels

@@ -43,6 +43,8 @@ struct GridDev {
     int max_probes;
     int nearest;     // radiance of the hit texel itself instead of the bilinear sample
     float inf;       // +INFINITY, set by the host (see min_nn)
+    int cmax[3];     // last cell index per axis: n - 2, or 0 with fewer than 8 probes
+    int few;         // fewer than 8 probes: one cell over the whole ray, every probe in its cage
 };
 
 // Layout of a probe's pyramid block (2 N^2 floats): every level keeps the row stride N of
@@ -491,18 +493,42 @@ struct RayResult {
 };
 
 // One camera ray (X, w unit): grid iterator over cells, 8 cage probes closest to the eye
-// first, fall-through on MISS and UNKNOWN.
-// cage order of one cell: the 8 corner codes (dx + 2 dy + 4 dz) sorted by squared distance
-// of the corner probe to the eye, ties by code, packed 3 bits each (first probe lowest)
+// first, fall-through on MISS and UNKNOWN.  A scene of fewer than 8 probes has no grid
+// iterator: one cell spans the whole ray and its cage is every probe (Methodology, Ray
+// Trace Using Multiple Probes: less than 8 probes).
+
+// Layout of a trace: a grid (one level), a two-level hierarchy, or fewer than 8 probes.
+enum { kGrid = 0, kTwoLevel = 1, kFew = 2 };
+
+// grid coordinates of cage entry c of cell `cell`: the corner with code c = dx + 2 dy + 4 dz,
+// or, with fewer than 8 probes, probe c itself
+__device__ __forceinline__ void cage_probe(const GridDev &g, bool few, const int cell[3], int c, int pc[3]) {
+    if (few) {
+        pc[0] = c % g.n[0];
+        pc[1] = (c / g.n[0]) % g.n[1];
+        pc[2] = c / (g.n[0] * g.n[1]);
+    } else {
+        pc[0] = cell[0] + (c & 1);
+        pc[1] = cell[1] + ((c >> 1) & 1);
+        pc[2] = cell[2] + (c >> 2);
+    }
+}
+
+// cage order of one cell: the 8 entry codes sorted by squared distance of their probe to
+// the eye, ties by code, packed 3 bits each (first probe lowest); with fewer than 8 probes
+// (Few) the codes past the last probe sort last
+template <bool Few>
 __device__ __forceinline__ uint32_t cage_order(const GridDev &g, const int cell[3], const float X[3]) {
     float key[8];
     int code[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        float dx = grid_coord(g, 0, cell[0] + (c & 1)) - X[0];
-        float dy = grid_coord(g, 1, cell[1] + ((c >> 1) & 1)) - X[1];
-        float dz = grid_coord(g, 2, cell[2] + (c >> 2)) - X[2];
-        key[c] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+        int pc[3];
+        cage_probe(g, Few, cell, c, pc);
+        float dx = grid_coord(g, 0, pc[0]) - X[0];
+        float dy = grid_coord(g, 1, pc[1]) - X[1];
+        float dz = grid_coord(g, 2, pc[2]) - X[2];
+        key[c] = (!Few || c < g.P) ? __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx)) : g.inf;
         code[c] = c;
     }
     // insertion sort, fully unrolled (stable: equal keys keep corner-code order)
@@ -526,7 +552,7 @@ __device__ __forceinline__ uint32_t cage_order(const GridDev &g, const int cell[
 }
 
 __device__ __forceinline__ int cell_index(const GridDev &g, const int cell[3]) {
-    return cell[0] + (g.n[0] - 1) * (cell[1] + (g.n[1] - 1) * cell[2]);
+    return cell[0] + (g.cmax[0] + 1) * (cell[1] + (g.cmax[1] + 1) * cell[2]);
 }
 
 // Coarse level of a two-level probe hierarchy (the paper shows a hierarchical scene
@@ -544,10 +570,12 @@ struct Level2 {
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // cage / ccage: optional per-view tables of cage_order() for every fine / coarse cell (the
-// eye is the same for all rays of a view).  Two: trace the coarse level of L2 as well.
-template <bool Wide, bool Two>
+// eye is the same for all rays of a view).  Layout: kGrid, kTwoLevel (trace the coarse
+// level of L2 as well) or kFew (g holds fewer than 8 probes).
+template <bool Wide, int Layout>
 __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], const float w[3],
                           const uint32_t *__restrict__ cage, const uint32_t *__restrict__ ccage, RayResult &out) {
+    constexpr bool Two = Layout == kTwoLevel, Few = Layout == kFew;
     out.status = ST_MISS;
     out.probe = -1;
     out.texel = -1;
@@ -568,7 +596,7 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float q = (X[a] - g.org[a]) * g.ispc[a];
-        cell[a] = min(max((int)floorf(q), 0), g.n[a] - 2);
+        cell[a] = min(max((int)floorf(q), 0), g.cmax[a]);
     }
     bool any_unknown = false, hit = false;
     ProbeResult hp;
@@ -581,19 +609,19 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             int pidx = -1;
-            if (w[a] > 0.0f && cell[a] + 1 <= g.n[a] - 2) pidx = cell[a] + 1;
+            if (w[a] > 0.0f && cell[a] + 1 <= g.cmax[a]) pidx = cell[a] + 1;
             else if (w[a] < 0.0f && cell[a] >= 1) pidx = cell[a];
             tn[a] = pidx >= 0 ? plane_t(grid_coord(g, a, pidx), X[a], iw[a]) : INFINITY;
         }
         float tb = fminf(fminf(fminf(tn[0], tn[1]), tn[2]), tfar);
-        uint32_t order = cage ? cage[cell_index(g, cell)] : cage_order(g, cell, X);
+        uint32_t order = cage ? cage[cell_index(g, cell)] : cage_order<Few>(g, cell, X);
         int ccell[3] = {0, 0, 0};
         uint32_t corder = 0;
         if (Two) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                ccell[a] = min(max(floor_div(cell[a] - L2.off[a], L2.ratio[a]), 0), L2.c.n[a] - 2);
-            corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_order(L2.c, ccell, X);
+                ccell[a] = min(max(floor_div(cell[a] - L2.off[a], L2.ratio[a]), 0), L2.c.cmax[a]);
+            corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_order<false>(L2.c, ccell, X);
         }
         // the cage of one level, closest to the eye first; true on a HIT
         auto cage_walk = [&](const GridDev &G, const int cl[3], uint32_t ord, int lev) -> bool {
@@ -601,7 +629,8 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
                 int c = (int)(ord & 7u);
                 ord >>= 3;
                 ProbeResult pr;
-                int pc[3] = {cl[0] + (c & 1), cl[1] + ((c >> 1) & 1), cl[2] + (c >> 2)};
+                int pc[3];
+                cage_probe(G, Few, cl, c, pc);
                 trace_probe<Wide>(G, pc[0], pc[1], pc[2], X, w, iw, ta, tb, pr);
                 if (pr.status == ST_HIT) {
                     hp = pr;

@@ -39,7 +39,7 @@ def test_host_side_argument_errors():
     assert lib.probe_grid_create(None, None, None, None, None) == 1
     assert b"NULL" in lib.pt_last_error()
     d = pt.PtGridDesc()
-    d.dims[:] = [1, 2, 2]  # too few probes along x
+    d.dims[:] = [0, 2, 2]  # no probes along x
     d.spacing[:] = [1, 1, 1]
     d.map_res = 64
     d.mip_levels = 4
@@ -48,6 +48,9 @@ def test_host_side_argument_errors():
     dummy = ctypes.c_void_p(16)
     assert lib.probe_grid_create(ctypes.byref(d), dummy, dummy, None, ctypes.byref(out)) == 1
     assert b"dims" in lib.pt_last_error() and not out.value
+    d.dims[:] = [4, 2, 1]  # 8 probes must form a grid with 2 or more per axis
+    assert lib.probe_grid_create(ctypes.byref(d), dummy, dummy, None, ctypes.byref(out)) == 1
+    assert b"per axis" in lib.pt_last_error() and not out.value
     d.dims[:] = [2, 2, 2]
     d.map_res = 48  # not a power of two
     assert lib.probe_grid_create(ctypes.byref(d), dummy, dummy, None, ctypes.byref(out)) == 1
