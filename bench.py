@@ -79,9 +79,22 @@ def cpu_baseline(probes, view):
     r = oracle.trace(g, o, d, nthreads=threads)
     dt = time.perf_counter() - t0
     n = len(o)
+    # one thread on every 8th ray of the frame
+    t1 = time.perf_counter()
+    oracle.trace(g, o[::8], d[::8], nthreads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=n / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
                 sample=f"full {view.width}x{view.height} frame ({n} rays), double precision, {threads} threads, "
-                       f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()))
+                       f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()),
+                one_thread={"value": len(o[::8]) / dt1 / 1e6, "unit": "Mrays/s",
+                            "sample": f"every 8th ray of the frame ({len(o[::8])} rays), {dt1:.1f} s"},
+                cpu_model=model, nproc=os.cpu_count())
 
 
 def differentiable(pt, synth, torch, np, steps=5):
@@ -149,6 +162,29 @@ def bake(pt, synth, torch, np, n_points=4_000_000, steps=5):
     return {"workload": f"{probes.n_probes} probes x {probes.N}^2 texels from {n_points} points (1080p room)",
             "ms": round(ms, 3), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 2),
             "filled_texels": round(float(torch.isfinite(out[0]).float().mean()), 4)}
+
+
+def paper_maps(pt, synth, torch, np, steps=10):
+    """The paper's map configuration: 4 probes (2x2x1, every probe per ray) of 2048^2 maps,
+    the march starting at the 128^2 low-resolution level, one 1920x1080 frame; and, for
+    comparison, the flat march (no low-resolution map)."""
+    scene, probes, views = synth.workload("paper")
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    va = pt.make_views(views)
+    rays = pt.n_rays(views)
+    out = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"),
+           torch.empty(rays, dtype=torch.uint8, device="cuda"), None)
+    res = {"workload": f"{probes.n_probes} probes (2x2x1) of {probes.N}^2 maps, pyramid to "
+                       f"{probes.N >> (probes.levels - 1)}^2; room of {len(scene.obj_type)} objects; "
+                       f"1 view of {views[0].width}x{views[0].height}", "rays": rays}
+    for name, lvl in (("low_res_128", probes.levels - 1), ("flat", 0)):
+        opts = pt.trace_opts(tile=(4, 16), start_level=lvl)
+        ms, _ = time_steps(lambda: pt.probe_trace(grid, rad, va, opts, out=out), steps, 2, torch)
+        res[name] = {"start_level": lvl, "value": round(rays / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s",
+                     "ms_per_frame": round(ms, 4)}
+    res["hit_frac"] = round(float((out[2] == 1).float().mean()), 4)
+    return res
 
 
 def large(pt, synth, torch, np, steps=3):
@@ -328,12 +364,15 @@ def main():
     if not args.no_extras:
         print("[bench] point-cloud bake", file=sys.stderr, flush=True)
         result["bake"] = bake(pt, synth, torch, np)
+        print("[bench] paper map configuration", file=sys.stderr, flush=True)
+        result["paper_maps"] = paper_maps(pt, synth, torch, np)
     if args.large:
         print("[bench] large two-level workload", file=sys.stderr, flush=True)
         result["large"] = large(pt, synth, torch, np)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(probes, view)
+        cb["one_thread"]["value"] = round(cb["one_thread"]["value"], 4)
         result["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(result), flush=True)
 

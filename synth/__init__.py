@@ -439,6 +439,10 @@ CONFIGS = {
                     views=dict(seed=2, n=64, walk=True)),
     "diff": dict(seed=3, dims=(16, 16, 8), spacing=1.0, N=256, levels=6, k_range=(20, 40),
                  target_seed=4, views=dict(seed=103, n=32, width=512, height=512)),
+    # the paper's map configuration: a few probes (2x2x1 over a 4 x 4 x 2 room) with 2048^2
+    # maps and a pyramid down to the 128^2 low-resolution map (5 levels)
+    "paper": dict(seed=8, dims=(2, 2, 1), spacing=2.0, N=2048, levels=5, k_range=(6, 12),
+                  views=dict(seed=108, n=1, width=1920, height=1080)),
     # two-level hierarchy over a city block: fine 64x64x16 probes (spacing 1) and coarse
     # 16x16x4 (spacing 4) whose planes are every 4th fine plane from the second
     "large": dict(seed=5, dims=(64, 64, 16), spacing=1.0, coarse_dims=(16, 16, 4), plane_off=1, ratio=4,

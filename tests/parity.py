@@ -57,12 +57,20 @@ def compare(gpu: dict, orc: dict, sel=None) -> dict:
         t_rel_max_agreeing=float(trel[agree & both_hit].max()) if (agree & both_hit).any() else 0.0,
         rgb_abs_max_agreeing=float(rgb_err[agree].max()) if agree.any() else 0.0,
         t_nonhit_finite=int(np.isfinite(t_g[st_g != oracle.HIT]).sum()),
+        # the closest call among the disagreeing rays: the smallest relative gap of a decision
+        # to its threshold (FP32 resolves about 1e-7)
+        score_max_disagreeing=float(orc["score"][dis].max()) if ("score" in orc and dis.any()) else 0.0,
     )
 
 
-def assert_parity(s: dict, label: str = ""):
+def assert_parity(s: dict, label: str = "", max_frac: float = MAX_DISAGREE, max_score: float | None = None):
+    """The acceptance above; `max_frac` replaces the disagreement budget where a test states
+    why, and `max_score` additionally bounds how close to its threshold the decisive
+    comparison of every disagreeing ray must have been."""
     info = {k: v for k, v in s.items() if k != "disagree_idx"}
     print(f"[parity] {label} {info}", flush=True)
     assert s["disagree_outside_margin"] == 0, (label, info)
-    assert s["disagree"] <= max(MAX_DISAGREE * s["n"], 1.0), (label, info)
+    assert s["disagree"] <= max(max_frac * s["n"], 1.0), (label, info)
     assert s["t_nonhit_finite"] == 0, (label, info)
+    if max_score is not None:
+        assert s["score_max_disagreeing"] <= max_score, (label, info)

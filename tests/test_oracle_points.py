@@ -87,7 +87,7 @@ def test_dense_cloud_approaches_the_analytic_bake():
     N = probes.N
     dist, nuv, rad, win = bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm)
     from test_oracle_scene import _texel_diameter
-    theta = _texel_diameter(N)[None, :]
+    theta = _texel_diameter(N, np.arange(N * N))[None, :]
     ra = probes.distance.reshape(len(dist), -1).astype(np.float64)
     rp = dist.reshape(len(dist), -1).astype(np.float64)
     dense = np.isfinite(rp) & (n / area * (ra * theta) ** 2 >= 20)

@@ -25,19 +25,17 @@ import synth
 from conftest import workload
 
 
-def _texel_diameter(N):
-    """Max corner-to-corner angle of every texel (radians), [N*N]."""
+def _texel_diameter(N, k):
+    """Max corner-to-corner angle (radians) of the texels with linear indices k."""
+    k = np.asarray(k, dtype=np.int64)
+    uk, inv = np.unique(k, return_inverse=True)
     e = np.linspace(-1, 1, N + 1)
-    corners = np.empty((N + 1, N + 1, 3))
-    for j in range(N + 1):
-        for i in range(N + 1):
-            corners[j, i] = oracle.oct_decode(np.array([e[i], e[j]]))
-    a = corners[:-1, :-1].reshape(-1, 3)
-    b = corners[1:, 1:].reshape(-1, 3)
-    c = corners[:-1, 1:].reshape(-1, 3)
-    d = corners[1:, :-1].reshape(-1, 3)
+    i, j = uk % N, uk // N
+    dec = lambda u, v: np.stack([oracle.oct_decode(np.array([a, b])) for a, b in zip(u, v)]).reshape(-1, 3)
+    a, b = dec(e[i], e[j]), dec(e[i + 1], e[j + 1])
+    c, d = dec(e[i + 1], e[j]), dec(e[i], e[j + 1])
     ang = lambda x, y: np.arccos(np.clip(np.sum(x * y, 1), -1, 1))
-    return np.maximum(ang(a, b), ang(c, d))
+    return np.maximum(ang(a, b), ang(c, d))[inv]
 
 
 def _discontinuity_mask(sid, dist, tau):
@@ -62,21 +60,23 @@ def _check(scene, probes, view, pixels=None):
     t_true, n_true, alb, ids = synth.cast(scene, o, d)
     N = probes.N
     tau = 8.0 / N
-    theta = _texel_diameter(N)
     disc = _discontinuity_mask(probes.extra["surface_id"], probes.distance, tau)
     hit = r["status"] == oracle.HIT
     assert np.all(np.isfinite(t_true))  # the room is closed
     cosw = np.abs(np.sum(n_true * d, 1))
     p = np.where(hit, r["probe"], 0)
     k = np.where(hit, r["texel"], 0)
-    rk = probes.distance[p].reshape(len(p), -1)[np.arange(len(p)), k].astype(np.float64)
+    rk = probes.distance.reshape(probes.n_probes, -1)[p, k].astype(np.float64)
+    theta = np.zeros(len(p))
+    if hit.any():
+        theta[hit] = _texel_diameter(N, k[hit])
     excluded = hit & ((cosw < 0.1) | disc[p, k])
     # camera-side surface edges: perturb the true hit across the ray by two footprints
     cand = np.nonzero(hit & ~excluded)[0]
     if len(cand):
         P = o[cand] + t_true[cand, None] * d[cand]
         rp = np.linalg.norm(P - np.stack([g.probe_position(q) for q in p[cand]]), axis=1)
-        F = 2.0 * theta[k[cand]] * np.maximum(rp, rk[cand])
+        F = 2.0 * theta[cand] * np.maximum(rp, rk[cand])
         dd = d[cand]
         a = np.where(np.abs(dd[:, 0:1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
         e1 = np.cross(dd, a)
@@ -89,7 +89,7 @@ def _check(scene, probes, view, pixels=None):
             near_edge |= (ids2 != ids[cand]) & jump
         excluded[cand[near_edge]] = True
     checked = hit & ~excluded
-    bound = 1.5 * rk * (theta[k] + tau) / np.maximum(cosw, 1e-12)
+    bound = 1.5 * rk * (theta + tau) / np.maximum(cosw, 1e-12)
     err = np.abs(r["t"] - t_true)
     fails = checked & (err > bound)
     return dict(n=len(hit), hit=hit.sum(), checked=checked.sum(), excluded=excluded.sum(), fails=fails.sum(),

@@ -50,7 +50,7 @@ def test_two_level_city_against_analytic_scene():
     assert np.all(np.isfinite(t_true))
     N = tl.fine.N
     tau = 8.0 / N
-    theta = _texel_diameter(N)
+    theta = _texel_diameter(N, np.arange(N * N))
     dist = np.concatenate([tl.fine.distance, tl.coarse.distance])
     sid = np.concatenate([tl.fine.extra["surface_id"], tl.coarse.extra["surface_id"]])
     pos = np.concatenate([synth.grid_positions(ps.dims, ps.origin[0], ps.spacing[0]) for ps in (tl.fine, tl.coarse)])
