@@ -110,7 +110,11 @@ def differentiable(pt, synth, torch, np, steps=5):
     del trad
     rays = pt.n_rays(views)
     fit = RadianceFit(grid, views, target)
-    losses = [fit.step().item()]  # warm-up
+    for _ in range(3):  # warm-up on a throw-away fit
+        fit.step()
+    del fit
+    fit = RadianceFit(grid, views, target)  # the timed run starts from the initial radiance
+    losses = [fit.step().item()]
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
