@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("status", "t", "rgb", "probe", "texel", "margin", "tests", "normals", "flat_tests", "rank",
-                 "taps", "wts", "score", "work")]
+                 "taps", "wts", "score", "work", "dtdr", "drgbdt")]
 
 
 def build_native(force: bool = True) -> str:
@@ -241,7 +241,8 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) 
                probe=np.empty(n, np.int32), texel=np.empty(n, np.int32), margin=np.empty(n, np.int32),
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),
                rank=np.empty(n, np.int32), taps=np.empty((n, 4), np.int32), wts=np.empty((n, 4), np.float64),
-               score=np.empty(n, np.float64), work=np.empty((n, 3), np.int32))
+               score=np.empty(n, np.float64), work=np.empty((n, 3), np.int32), dtdr=np.empty(n, np.float64),
+               drgbdt=np.empty((n, 3), np.float64))
     out = _Out()
     for k, v in res.items():
         setattr(out, k, v.ctypes.data)
@@ -286,6 +287,31 @@ def vjp(grid, result: dict, grad_rgb: np.ndarray) -> np.ndarray:
     for k in range(4):
         np.add.at(g, flat[:, k], wts[:, k:k + 1] * gr)
     return g.reshape(P, N, N, 3)
+
+
+def vjp_distance(grid, result: dict, grad_rgb=None, grad_t=None) -> np.ndarray:
+    """Adjoint of the stored distances with the classification held fixed (an extension
+    beyond the paper, which renders forward only).  A HIT ray depends on the distance r of
+    its hit texel only, through the hit distance t: dt/dr is 1 for the eye-aligned lookup,
+    0 when the hit is the texel's entry point, r / sqrt(r^2 - d_perp^2) for the root of
+    |X - O + t w| = r; the bilinear radiance sample moves with the hit point, d rgb/dt.  So
+    dL/dr[p][k] = sum over HIT rays on (p, k) of dt/dr (dL/dt + dL/drgb . drgb/dt), in
+    double.  [P][N][N]."""
+    grids = grid if isinstance(grid, (list, tuple)) else (grid,)
+    P = sum(gr.distance.shape[0] for gr in grids)
+    N = grids[0].N
+    g = np.zeros(P * N * N, dtype=np.float64)
+    hit = result["status"] == HIT
+    if not np.any(hit):
+        return g.reshape(P, N, N)
+    up = np.zeros(int(hit.sum()))
+    if grad_t is not None:
+        up += np.asarray(grad_t, dtype=np.float64).reshape(-1)[hit]
+    if grad_rgb is not None:
+        up += np.sum(np.asarray(grad_rgb, dtype=np.float64).reshape(-1, 3)[hit] * result["drgbdt"][hit], axis=1)
+    flat = result["probe"][hit].astype(np.int64) * (N * N) + result["texel"][hit].astype(np.int64)
+    np.add.at(g, flat, result["dtdr"][hit] * up)
+    return g.reshape(P, N, N)
 
 
 # ---------------------------------------------------------------------------------------------

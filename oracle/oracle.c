@@ -121,6 +121,8 @@ typedef struct {
     double *wts;       /* [n][4] bilinear weights */
     double *score;     /* [n] min over decisions of gap / error scale (nullable) */
     int32_t *work;     /* [n][3] probe traces, pieces marched, cells visited (nullable) */
+    double *dtdr;      /* [n] d t_hit / d r of the hit texel, classification held (nullable) */
+    double *drgbdt;    /* [n][3] d rgb / d t_hit: the radiance sample moving with the hit point (nullable) */
 } out_t;
 
 /* ------------------------------------------------------------------------------------
@@ -463,11 +465,48 @@ static void bilinear_taps(double u, double v, int N, int idx[4], double wt[4]) {
     }
 }
 
+/* d/dt of the bilinear radiance sample at oct(q + t w) at t = 0: the octahedral encode and
+ * the bilinear weights differentiated by the chain rule (each piece is smooth; the fold of
+ * the lower hemisphere and texel-centre lines are kinks, where one side is taken) */
+static void radiance_dt(int N, const float *R, const double q[3], const double w[3], double out[3]) {
+    double sx = q[0] >= 0 ? 1.0 : -1.0, sy = q[1] >= 0 ? 1.0 : -1.0, sz = q[2] >= 0 ? 1.0 : -1.0;
+    double L = fabs(q[0]) + fabs(q[1]) + fabs(q[2]);
+    double dL = sx * w[0] + sy * w[1] + sz * w[2];
+    double px = q[0] / L, py = q[1] / L, pz = q[2] / L;
+    double dpx = (w[0] - px * dL) / L, dpy = (w[1] - py * dL) / L;
+    double u, v, du, dv;
+    if (pz >= 0) {
+        u = px; v = py; du = dpx; dv = dpy;
+    } else {
+        double spx = px >= 0 ? 1.0 : -1.0, spy = py >= 0 ? 1.0 : -1.0;
+        u = (1.0 - fabs(py)) * spx;
+        v = (1.0 - fabs(px)) * spy;
+        du = -spx * spy * dpy;
+        dv = -spy * spx * dpx;
+    }
+    int idx[4];
+    double wt[4];
+    bilinear_taps(u, v, N, idx, wt);
+    double x = 0.5 * (u + 1.0) * N - 0.5, y = 0.5 * (v + 1.0) * N - 0.5;
+    double fx = x - floor(x), fy = y - floor(y);
+    double dx = 0.5 * N * du, dy = 0.5 * N * dv;
+    double dw[4] = {-dx * (1.0 - fy) - (1.0 - fx) * dy, dx * (1.0 - fy) - fx * dy, -dx * fy + (1.0 - fx) * dy,
+                    dx * fy + fx * dy};
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0;
+        for (int k = 0; k < 4; ++k) acc += dw[k] * (double)R[3 * idx[k] + c];
+        out[c] = acc;
+    }
+}
+
 typedef struct {
     int status;
     int texel;
     double t;       /* hit distance along the ray */
     double dirp[3]; /* direction from the probe to the hit point */
+    double dtdr;    /* d t / d r_k with the classification held: 1 for the eye lookup, 0 for an
+                       entry hit, r / sqrt(r^2 - d_perp^2) for the root */
+    int eye;        /* hit by the eye-aligned lookup (the sample direction is w itself) */
     int tests, normals, flat_tests, pieces;
 } presult_t;
 
@@ -515,6 +554,8 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
             res->status = ST_HIT;
             res->texel = j * N + i;
             res->t = rk;
+            res->dtdr = 1.0;
+            res->eye = 1;
             memcpy(res->dirp, w, sizeof(double) * 3);
         }
         return;
@@ -581,6 +622,7 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
         double th;
         if (ff.rin >= rk) {
             th = ff.tin;
+            res->dtdr = 0.0; /* the entry point does not move with r */
             /* the entry crossing's condition scale decides how well t is known */
             if (1e-2 * ff.Ein > fabs(th)) mc->bits |= MG_THIT;
         } else {
@@ -593,6 +635,8 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
             if (sq <= 1e-2 * rk) mc->bits |= MG_THIT;
             if (b <= 0) th = -b + sq;
             else th = (rk - dist) * (rk + dist) / (b + sq);
+            /* t = -b + sqrt(r^2 - d_perp^2): dt/dr = r / sqrt(...) (infinite at tangency) */
+            res->dtdr = sq > 0 ? rk / sq : INFINITY;
         }
         res->t = th;
         for (int a = 0; a < 3; ++a) res->dirp[a] = r.Xp[a] + th * w[a];
@@ -758,6 +802,12 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
                     }
                     if (out->taps)
                         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
+                    if (out->dtdr) out->dtdr[ri] = pr.dtdr;
+                    if (out->drgbdt) {
+                        double dr[3] = {0, 0, 0};
+                        if (!o->nearest && !pr.eye) radiance_dt(G->N, R, pr.dirp, w, dr);
+                        for (int ch = 0; ch < 3; ++ch) out->drgbdt[3 * ri + ch] = dr[ch];
+                    }
                     goto done;
                 }
                 if (pr.status == ST_UNKNOWN) any_unknown = 1;
@@ -777,6 +827,9 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
     for (int ch = 0; ch < 3; ++ch) out->rgb[3 * ri + ch] = o->background[ch];
     if (out->taps)
         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = -1; out->wts[4 * ri + k] = 0; }
+    if (out->dtdr) out->dtdr[ri] = 0;
+    if (out->drgbdt)
+        for (int ch = 0; ch < 3; ++ch) out->drgbdt[3 * ri + ch] = 0;
 done:
     out->margin[ri] = mc.bits;
     if (out->score) out->score[ri] = mc.score;
