@@ -136,12 +136,26 @@ def differentiable(pt, synth, torch, np, steps=5):
     e1.record()
     torch.cuda.synchronize()
     ms_fb = e0.elapsed_time(e1) / steps
+    # gradient through the stored distances: forward (rgb and t) + distance adjoint
+    del g
+    gd = torch.zeros((grid.P, grid.N, grid.N), device="cuda")
+    gt = torch.randn(rays, device="cuda")
+    outs = pt._alloc_outputs(rays, gr.device, True, False, False)
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, storage, va, po, out=outs)
+        pt.probe_trace_backward_distance(grid, storage, va, gr, gt, gd, po)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_geo = e0.elapsed_time(e1) / steps
     return {"workload": "16x16x8 probes, 256^2 maps (6 levels), 32 views of 512x512; FP32 master, FP16 storage; "
                         "Adam lr 1e-2 from 0.5",
             "rays_per_step": rays, "adam_step_ms": round(ms, 3),
             "adam_step_mrays_s": round(rays / (ms * 1e-3) / 1e6, 2),
             "fwd_bwd_kernels_ms": round(ms_fb, 3), "fwd_bwd_mrays_s": round(rays / (ms_fb * 1e-3) / 1e6, 2),
             "launch": "one persistent launch over the 32 views, forward and adjoint",
+            "geometry_fwd_bwd_kernels_ms": round(ms_geo, 3),
+            "geometry_fwd_bwd_mrays_s": round(rays / (ms_geo * 1e-3) / 1e6, 2),
             "loss": [round(x, 6) for x in losses]}
 
 

@@ -204,6 +204,37 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
                                const float *grad_rgb_dev, float *grad_radiance_dev, const pt_trace_opts *opts,
                                void *stream);
 
+/* Adjoint of probe_trace with respect to the stored distances (gradients through geometry;
+ * an extension beyond the paper, which renders forward only), the classification held
+ * fixed: which probe and texel a ray hits, and whether it is HIT, do not move.  A HIT ray
+ * depends on the distance r of its hit texel only, through its hit distance t:
+ *   dt/dr = 1 for the eye-aligned lookup (t = r), 0 when the hit is the entry point of the
+ *   firing texel, r / sqrt(r^2 - d_perp^2) for the root of |X - O + t w| = r (+INF at
+ *   tangency);
+ * and its rgb moves with t as the bilinear sample direction X - O + t w moves (drgb/dt by
+ * the chain rule through the octahedral encode and the bilinear weights; zero for the eye
+ * lookup and with PT_FLAG_NEAREST).  Recomputes the trace, then for every HIT ray adds
+ *   dt/dr (grad_t + grad_rgb . drgb/dt)
+ * to grad_distance_dev[probe][texel].
+ *   radiance_dev       [P][N][N][3] FP16 bits, the radiance the forward sampled (needed
+ *                      when grad_rgb_dev is given)
+ *   grad_rgb_dev       [rays][3] FP32 or NULL; grad_t_dev [rays] FP32 or NULL (not both
+ *                      NULL); same ray order as probe_trace
+ *   grad_distance_dev  [P][N][N] FP32, ACCUMULATED into (+=); caller zeroes it.  In a
+ *                      two-level hierarchy P counts both levels, fine first.
+ * Launch forms, summation order and stream rules as for probe_trace_backward.
+ * Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace_backward_distance(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
+                                        int32_t n_views, const float *grad_rgb_dev, const float *grad_t_dev,
+                                        float *grad_distance_dev, const pt_trace_opts *opts, void *stream);
+
+/* Replace the distance maps of a grid (level 0 of every probe) from distance_dev
+ * ([P][N][N] FP32, this grid's probes only) and rebuild its MIN pyramid, on `stream`; the
+ * normals stay.  For optimising the geometry: the caller keeps distance_dev alive until
+ * `stream` has passed this call, and orders it before the traces that should see it.
+ * Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_grid_set_distance(pt_grid *grid, const float *distance_dev, void *stream);
+
 /* Choose tile shape, pyramid start level and launch form (per-view launches or one
  * persistent launch; PT_FLAG_GRAPH is kept if the caller set it) for these views by timing
  * candidate launches on `stream` (synchronous; writes into rgb_dev, which must hold the

@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("status", "t", "rgb", "probe", "texel", "margin", "tests", "normals", "flat_tests", "rank",
-                 "taps", "wts", "score", "work", "dtdr", "drgbdt")]
+                 "taps", "wts", "score", "work", "dtdr", "drgbdt", "kink")]
 
 
 def build_native(force: bool = True) -> str:
@@ -242,7 +242,7 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) 
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),
                rank=np.empty(n, np.int32), taps=np.empty((n, 4), np.int32), wts=np.empty((n, 4), np.float64),
                score=np.empty(n, np.float64), work=np.empty((n, 3), np.int32), dtdr=np.empty(n, np.float64),
-               drgbdt=np.empty((n, 3), np.float64))
+               drgbdt=np.empty((n, 3), np.float64), kink=np.empty(n, np.int32))
     out = _Out()
     for k, v in res.items():
         setattr(out, k, v.ctypes.data)

@@ -123,6 +123,8 @@ typedef struct {
     int32_t *work;     /* [n][3] probe traces, pieces marched, cells visited (nullable) */
     double *dtdr;      /* [n] d t_hit / d r of the hit texel, classification held (nullable) */
     double *drgbdt;    /* [n][3] d rgb / d t_hit: the radiance sample moving with the hit point (nullable) */
+    int32_t *kink;     /* [n] bit 0: the hit is within the margin of switching between the texel's
+                          entry point and the root, where t(r) is continuous but dt/dr jumps (nullable) */
 } out_t;
 
 /* ------------------------------------------------------------------------------------
@@ -507,6 +509,7 @@ typedef struct {
     double dtdr;    /* d t / d r_k with the classification held: 1 for the eye lookup, 0 for an
                        entry hit, r / sqrt(r^2 - d_perp^2) for the root */
     int eye;        /* hit by the eye-aligned lookup (the sample direction is w itself) */
+    int kink;       /* bit 0: rho_in within the margin of r (entry point vs root) */
     int tests, normals, flat_tests, pieces;
 } presult_t;
 
@@ -620,6 +623,7 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
         res->status = ST_HIT;
         /* hit distance: entry point if already at/behind the surface, else where rho = r */
         double th;
+        if (fabs(ff.rin - rk) <= mc->delta * (rk + r.S + fabs(ff.tin) + drho_at(&r, ff.tin) * ff.Ein)) res->kink |= 1;
         if (ff.rin >= rk) {
             th = ff.tin;
             res->dtdr = 0.0; /* the entry point does not move with r */
@@ -803,6 +807,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
                     if (out->taps)
                         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
                     if (out->dtdr) out->dtdr[ri] = pr.dtdr;
+                    if (out->kink) out->kink[ri] = pr.kink;
                     if (out->drgbdt) {
                         double dr[3] = {0, 0, 0};
                         if (!o->nearest && !pr.eye) radiance_dt(G->N, R, pr.dirp, w, dr);
@@ -828,6 +833,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
     if (out->taps)
         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = -1; out->wts[4 * ri + k] = 0; }
     if (out->dtdr) out->dtdr[ri] = 0;
+    if (out->kink) out->kink[ri] = 0;
     if (out->drgbdt)
         for (int ch = 0; ch < 3; ++ch) out->drgbdt[3 * ri + ch] = 0;
 done:

@@ -25,8 +25,9 @@ PT_FLAG_NEAREST = 4
 PT_FLAG_WIDE = 8
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
-            "probe_grid_set_coarse", "probe_bake_points",
-            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_autotune", "pt_last_error")
+            "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",
+            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_distance",
+            "probe_autotune", "pt_last_error")
 
 
 class PtGridDesc(ctypes.Structure):
@@ -76,9 +77,12 @@ def load_library(path: str = LIB_PATH):
     lib.probe_trace_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_backward.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_autotune.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_trace_backward_distance.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp,
+                                                  ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_grid_set_distance.argtypes = [vp, vp, vp]
     for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
-                 "probe_trace", "probe_trace_rays",
-                 "probe_trace_backward", "probe_autotune"):
+                 "probe_trace", "probe_trace_rays", "probe_grid_set_distance",
+                 "probe_trace_backward", "probe_trace_backward_distance", "probe_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
     lib.pt_last_error.restype = ctypes.c_char_p
@@ -199,6 +203,14 @@ class ProbeGrid:
         _check(lib.probe_grid_set_coarse(self.handle, coarse.handle if coarse is not None else None, off, rat))
         self.coarse = coarse  # keeps it alive while attached
 
+    def set_distance(self, distance, stream=None):
+        """Replace this grid's distance maps ([P,N,N] FP32 on the device) and rebuild its MIN
+        pyramid; the tensor must stay alive until the stream has passed the call."""
+        lib = load_library()
+        distance = _dev_tensor(distance, torch.float32, "distance")
+        _need(distance, self.P * self.N * self.N, "distance")
+        _check(lib.probe_grid_set_distance(self.handle, _ptr(distance), _stream(stream)))
+
     @property
     def P_total(self) -> int:
         """Probes of the radiance layout: the fine ones, then the coarse level's."""
@@ -312,6 +324,31 @@ def probe_trace_backward(grid: ProbeGrid, views, grad_rgb, grad_radiance, opts: 
     return grad_radiance
 
 
+def probe_trace_backward_distance(grid: ProbeGrid, radiance_half, views, grad_rgb, grad_t, grad_distance,
+                                  opts: PtTraceOpts | None = None, stream=None):
+    """Accumulate (+=) the gradient of sum(grad_rgb * rgb) + sum(grad_t * t) with respect to
+    the stored distances into grad_distance [P_total,N,N] FP32, the classification held
+    fixed.  grad_rgb or grad_t may be None (not both)."""
+    lib = load_library()
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    grad_distance = _dev_tensor(grad_distance, torch.float32, "grad_distance")
+    _need(grad_distance, grid.P_total * grid.N * grid.N, "grad_distance")
+    if grad_rgb is not None:
+        grad_rgb = _dev_tensor(grad_rgb, torch.float32, "grad_rgb")
+        _need(grad_rgb, 3 * rays, "grad_rgb")
+        radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+        _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
+    if grad_t is not None:
+        grad_t = _dev_tensor(grad_t, torch.float32, "grad_t")
+        _need(grad_t, rays, "grad_t")
+    _check(lib.probe_trace_backward_distance(
+        grid.handle, _ptr(radiance_half) if grad_rgb is not None else None, va, len(va),
+        _ptr(grad_rgb) if grad_rgb is not None else None, _ptr(grad_t) if grad_t is not None else None,
+        _ptr(grad_distance), ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return grad_distance
+
+
 def probe_autotune(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None = None, stream=None):
     """Time candidate tile shapes and start levels; returns the tuned options."""
     lib = load_library()
@@ -347,3 +384,42 @@ class ProbeTraceFn(torch.autograd.Function):
         g = torch.zeros(ctx.shape, dtype=torch.float32, device=grad_rgb.device)
         probe_trace_backward(ctx.grid, ctx.views, grad_rgb.contiguous().float(), g, ctx.opts)
         return g, None, None, None
+
+
+
+class ProbeGeometryFn(torch.autograd.Function):
+    """(rgb, t) = trace(distance, radiance) of a single-level grid, with the classification
+    held fixed in the backward.
+
+    forward: the grid's distance maps are replaced by `distance` ([P,N,N] FP32; the MIN
+    pyramid is rebuilt) and the FP32 master radiance is rounded to FP16 storage;
+    backward: probe_trace_backward_distance for the distances (through t and the motion of
+    the radiance sample), probe_trace_backward for the radiance (straight through the FP16
+    rounding).  t is +inf for rays that are not HIT: a loss on t masks them (they get no
+    gradient either way)."""
+
+    @staticmethod
+    def forward(ctx, distance, master, grid, views, opts=None):
+        if grid.P_total != grid.P:
+            raise ProbeTraceError("ProbeGeometryFn: single-level grids only")
+        grid.set_distance(distance.detach().contiguous())
+        storage = master.detach().to(torch.float16).contiguous()
+        va = views if isinstance(views, ctypes.Array) else make_views(views)
+        res = probe_trace(grid, storage, va, opts, want_t=True, want_status=False, want_hit=False)
+        ctx.grid, ctx.views, ctx.opts, ctx.storage = grid, va, opts, storage
+        ctx.dshape, ctx.mshape = distance.shape, master.shape
+        return res["rgb"], res["t"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_t):
+        gd = gm = None
+        dev = ctx.storage.device
+        grad_rgb = grad_rgb.contiguous().float() if grad_rgb is not None else None
+        grad_t = grad_t.contiguous().float() if grad_t is not None else None
+        if ctx.needs_input_grad[0] and (grad_rgb is not None or grad_t is not None):
+            gd = torch.zeros(ctx.dshape, dtype=torch.float32, device=dev)
+            probe_trace_backward_distance(ctx.grid, ctx.storage, ctx.views, grad_rgb, grad_t, gd, ctx.opts)
+        if ctx.needs_input_grad[1] and grad_rgb is not None:
+            gm = torch.zeros(ctx.mshape, dtype=torch.float32, device=dev)
+            probe_trace_backward(ctx.grid, ctx.views, grad_rgb, gm, ctx.opts)
+        return gd, gm, None, None, None

@@ -446,19 +446,77 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
     }
 }
 
-// One wavefront's tile of the adjoint: recompute the trace, then scatter w_tap * grad_rgb
-// into the radiance gradient.  All 64 lanes call it together (the scatter is collective).
-template <bool W, int T>
+// Single-channel form of the scatter above: one (key, value) per lane, at most 64
+// distinct keys per wave.  All 64 lanes must arrive here together.
+__device__ __forceinline__ void wave_scatter_add1(float *__restrict__ grad, int64_t key, float val) {
+    const int lane = threadIdx.x & 63;
+    bool pend = key >= 0;
+    for (int guard = 0; guard < 64; ++guard) {
+        unsigned long long m = __ballot(pend);
+        if (m == 0ull) break;
+        int leader = __ffsll(m) - 1;
+        int lo = __shfl((int)(key & 0xffffffff), leader, 64);
+        int hi = __shfl((int)(key >> 32), leader, 64);
+        int64_t lkey = ((int64_t)hi << 32) | (uint32_t)lo;
+        bool take = pend && key == lkey;
+        float s = take ? val : 0.0f;
+        pend = pend && !take;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == leader) atomicAdd(grad + lkey, s);
+    }
+}
+
+// What an adjoint launch reads and writes.  Radiance adjoint: grad_rgb -> grad_out
+// [P][N][N][3].  Distance adjoint: grad_rgb and/or grad_t (either may be NULL) -> grad_out
+// [P][N][N], reading the radiance the forward sampled.
+struct AdjointIO {
+    const float *grad_rgb;
+    const float *grad_t;
+    const uint16_t *rad;
+    float *grad_out;
+};
+
+// One wavefront's tile of an adjoint: recompute the trace, then scatter.  Geo = false:
+// w_tap * grad_rgb into the radiance gradient.  Geo = true: dt/dr (grad_t + grad_rgb .
+// drgb/dt) into the distance of the hit texel.  All 64 lanes call it together (the scatter
+// is collective).
+template <bool W, int T, bool Geo>
 __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2, const ViewDev &v, int tile,
                                               const uint32_t *__restrict__ cage,
-                                              const uint32_t *__restrict__ ccage,
-                                              const float *__restrict__ grad_rgb, float *__restrict__ grad_rad,
-                                              int tw, int th) {
+                                              const uint32_t *__restrict__ ccage, const AdjointIO &io, int tw,
+                                              int th) {
     int lane = threadIdx.x & 63;
     int x = (tile % v.tiles_x) * tw + lane % tw;
     int y = (tile / v.tiles_x) * th + lane / tw;
+    if (Geo) {
+        int64_t key = -1;
+        float val = 0.0f;
+        if (x < v.W && y < v.H) {
+            float w[3];
+            camera_ray(v, x, y, w);
+            RayResult r;
+            trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
+            if (r.status == ST_HIT && r.dtdr != 0.0f) {
+                int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
+                float up = io.grad_t ? io.grad_t[ray] : 0.0f;
+                if (io.grad_rgb) {
+                    float drgb[3];
+                    hit_radiance_dt(g, io.rad, r, w, drgb);  // rad spans both levels (probe ids too)
+                    up = __fmaf_rn(io.grad_rgb[3 * ray + 2], drgb[2],
+                                   __fmaf_rn(io.grad_rgb[3 * ray + 1], drgb[1],
+                                             __fmaf_rn(io.grad_rgb[3 * ray], drgb[0], up)));
+                }
+                val = r.dtdr * up;
+                if (val != 0.0f) key = (int64_t)r.probe * g.N * g.N + r.texel;
+            }
+        }
+        wave_scatter_add1(io.grad_out, key, val);
+        return;
+    }
     int64_t key[4] = {-1, -1, -1, -1};
     float val[4][3] = {};
+    const float *__restrict__ grad_rgb = io.grad_rgb;
     if (x < v.W && y < v.H) {
         float w[3];
         camera_ray(v, x, y, w);
@@ -480,30 +538,28 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
             }
         }
     }
-    wave_scatter_add(grad_rad, key, val);
+    wave_scatter_add(io.grad_out, key, val);
 }
 
-// Adjoint: recompute the trace, scatter w_tap * grad_rgb into the radiance gradient.
-template <bool W, int T>
+// Adjoint of one view (radiance or, with Geo, distances); one tile per wavefront.
+template <bool W, int T, bool Geo>
 PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
-                                const uint32_t *__restrict__ ccage, const float *__restrict__ grad_rgb,
-                                float *__restrict__ grad_rad, int tw, int th) {
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                const uint32_t *__restrict__ ccage, AdjointIO io, int tw, int th) {
+    int wave = threadIdx.x >> 6;
     int nb = gridDim.x;
     int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
     int tiles_y = (v.H + th - 1) / th;
     if (tile >= v.tiles_x * tiles_y) return;  // whole wavefronts only
-    backward_tile<W, T>(g, L2, v, tile, cage, ccage, grad_rgb, grad_rad, tw, th);
+    backward_tile<W, T, Geo>(g, L2, v, tile, cage, ccage, io, tw, th);
 }
 
 // Persistent adjoint over many views: wavefronts pop tiles of all views from a device
 // counter (views sorted by tile_begin) until the queue is empty.
-template <bool W, int T>
+template <bool W, int T, bool Geo>
 PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
                                       const uint32_t *__restrict__ cage, int cells,
                                       const uint32_t *__restrict__ ccage, int ccells, int total_tiles,
-                                      int *counter, const float *__restrict__ grad_rgb,
-                                      float *__restrict__ grad_rad, int tw, int th) {
+                                      int *counter, AdjointIO io, int tw, int th) {
     int lane = threadIdx.x & 63;
     for (;;) {
         int tile = 0;
@@ -516,8 +572,8 @@ PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__res
             if (views[mid].tile_begin <= tile) lo = mid;
             else hi = mid - 1;
         }
-        backward_tile<W, T>(g, L2, views[lo], tile - views[lo].tile_begin, cage + (int64_t)lo * cells,
-                            T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr, grad_rgb, grad_rad, tw, th);
+        backward_tile<W, T, Geo>(g, L2, views[lo], tile - views[lo].tile_begin, cage + (int64_t)lo * cells,
+                                 T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr, io, tw, th);
     }
 }
 
@@ -855,11 +911,10 @@ extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance
     return PT_OK;
 }
 
-extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views_host, int32_t n_views,
-                                          const float *grad_rgb_dev, float *grad_radiance_dev,
-                                          const pt_trace_opts *opts, void *stream) {
-    if (!g || !grad_rgb_dev || !grad_radiance_dev)
-        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
+// Adjoint launches shared by the radiance and the distance adjoint (Geo).
+template <bool Geo>
+static pt_status launch_adjoint(const pt_grid *g, const pt_view *views_host, int32_t n_views, const AdjointIO &io,
+                                const pt_trace_opts *opts, void *stream) {
     int tw, th;
     pt_status st = tile_shape(opts, tw, th);
     if (st != PT_OK) return st;
@@ -888,9 +943,9 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
         launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, mg->counter);
 #define PT_LAUNCH(W, T)                                                                                          \
-    hipLaunchKernelGGL((k_backward_persistent<W, T>), dim3(persistent_blocks(g)), dim3(256), 0, s, c.d, c.L2,   \
-                       mg->views_dev, n_views, mg->cage, g->cells, mg->ccage, c.ccells, tiles, mg->counter,     \
-                       grad_rgb_dev, grad_radiance_dev, tw, th)
+    hipLaunchKernelGGL((k_backward_persistent<W, T, Geo>), dim3(persistent_blocks(g)), dim3(256), 0, s, c.d,     \
+                       c.L2, mg->views_dev, n_views, mg->cage, g->cells, mg->ccage, c.ccells, tiles, mg->counter, \
+                       io, tw, th)
         PT_DISPATCH(c, PT_LAUNCH);
 #undef PT_LAUNCH
         HIP_TRY(hipGetLastError());
@@ -903,10 +958,53 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
         uint32_t *ccage = c.two ? mg->ccage + (int64_t)i * c.ccells : nullptr;
         launch_cage_tables(g, c, nullptr, vd[i], 1, cage, ccage, s);
 #define PT_LAUNCH(W, T)                                                                                        \
-    hipLaunchKernelGGL((k_backward_view<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], cage, ccage,      \
-                       grad_rgb_dev, grad_radiance_dev, tw, th)
+    hipLaunchKernelGGL((k_backward_view<W, T, Geo>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], cage, ccage, \
+                       io, tw, th)
         PT_DISPATCH(c, PT_LAUNCH);
 #undef PT_LAUNCH
+    }
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views_host, int32_t n_views,
+                                          const float *grad_rgb_dev, float *grad_radiance_dev,
+                                          const pt_trace_opts *opts, void *stream) {
+    if (!g || !grad_rgb_dev || !grad_radiance_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
+    AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev};
+    return launch_adjoint<false>(g, views_host, n_views, io, opts, stream);
+}
+
+extern "C" pt_status probe_trace_backward_distance(const pt_grid *g, const uint16_t *radiance_dev,
+                                                   const pt_view *views_host, int32_t n_views,
+                                                   const float *grad_rgb_dev, const float *grad_t_dev,
+                                                   float *grad_distance_dev, const pt_trace_opts *opts,
+                                                   void *stream) {
+    if (!g || !grad_distance_dev || (!grad_rgb_dev && !grad_t_dev) || (grad_rgb_dev && !radiance_dev))
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward_distance: NULL argument");
+    AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev};
+    return launch_adjoint<true>(g, views_host, n_views, io, opts, stream);
+}
+
+// level 0 of every probe from a new distance map, then the MIN pyramid above it
+__global__ void k_pack_distance(const float *__restrict__ dist, float *__restrict__ pyr, int N, int64_t stride,
+                                int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int64_t NN = (int64_t)N * N;
+    pyr[(g / NN) * stride + g % NN] = dist[g];
+}
+
+extern "C" pt_status probe_grid_set_distance(pt_grid *g, const float *distance_dev, void *stream) {
+    if (!g || !distance_dev) return fail(PT_ERR_INVALID_ARGUMENT, "probe_grid_set_distance: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t total = (int64_t)g->P * g->N * g->N;
+    hipLaunchKernelGGL(k_pack_distance, dim3(blocks_for(total, 256)), dim3(256), 0, s, distance_dev, g->pyr, g->N,
+                       g->stride, total);
+    for (int l = 1; l < g->Lc; ++l) {
+        int64_t tl = (int64_t)g->P * (int64_t)(g->N >> l) * (g->N >> l);
+        hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, g->N, l, g->stride, tl);
     }
     HIP_TRY(hipGetLastError());
     return PT_OK;

@@ -490,6 +490,9 @@ struct RayResult {
     int texel;
     float t;
     float q[3];  // hit point relative to the hit probe
+    float dtdr;  // d t / d r of the hit texel with the classification held (the adjoint of
+                 // the distances reads it; the forward kernels drop it)
+    bool eye;    // resolved by the eye lookup: the sample direction is w itself
 };
 
 // One camera ray (X, w unit): grid iterator over cells, 8 cage probes closest to the eye
@@ -580,6 +583,8 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
     out.probe = -1;
     out.texel = -1;
     out.t = INFINITY;
+    out.dtdr = 0.0f;
+    out.eye = false;
     const float iw[3] = {frcp(w[0]), frcp(w[1]), frcp(w[2])};
     // until the ray leaves the scene box (slightly enlarged)
     float tfar = INFINITY;
@@ -668,6 +673,8 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
         out.q[0] = w[0];
         out.q[1] = w[1];
         out.q[2] = w[2];
+        out.dtdr = 1.0f;
+        out.eye = true;
         return;
     }
     float Xp[3];
@@ -677,6 +684,7 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
     float th;
     if (hp.rin2 >= r * r) {
         th = hp.tin;  // entered the texel beyond the stored distance: the hit is the entry
+        out.dtdr = 0.0f;
     } else {
         // larger root of |Xp + t w| = r, cancellation-free
         float d2 = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0]));
@@ -689,6 +697,7 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const float X[3], 
         float sq = sqrtf(disc);
         float dist = sqrtf(d2);
         th = b <= 0.0f ? sq - b : ((r - dist) * (r + dist)) / (b + sq);
+        out.dtdr = r * frcp(sq);  // t = sq - b with sq = sqrt(r^2 - d_perp^2); +inf at tangency
     }
     out.t = th;
     out.q[0] = __fmaf_rn(th, w[0], Xp[0]);
@@ -734,6 +743,49 @@ __device__ __forceinline__ void hit_taps(const GridDev &g, const RayResult &r, i
     float u, v;
     oct_encode(r.q[0], r.q[1], r.q[2], u, v);
     bilinear_taps(u, v, g.N, idx, wt);
+}
+
+// d rgb / d t_hit: the bilinear sample at oct(q), q = X - O + t w, moves along w as t
+// moves.  Chain rule through the octahedral encode (q / |q|_1, folded below the equator) and
+// the bilinear weights; zero for the eye lookup (the sample direction is w) and for nearest
+// radiance.  At the fold and on texel-centre lines (kinks) one side's derivative is taken.
+__device__ __forceinline__ void hit_radiance_dt(const GridDev &g, const uint16_t *__restrict__ rad,
+                                                const RayResult &r, const float w[3], float drgb[3]) {
+    drgb[0] = drgb[1] = drgb[2] = 0.0f;
+    if (g.nearest || r.eye) return;
+    const float *q = r.q;
+    float sx = sgnp(q[0]), sy = sgnp(q[1]), sz = sgnp(q[2]);
+    float iL = frcp((fabsf(q[0]) + fabsf(q[1])) + fabsf(q[2]));
+    float dL = __fmaf_rn(sz, w[2], __fmaf_rn(sy, w[1], sx * w[0]));
+    float px = q[0] * iL, py = q[1] * iL, pz = q[2] * iL;
+    float dpx = __fmaf_rn(-px, dL, w[0]) * iL;  // d(q_x / |q|_1) / dt
+    float dpy = __fmaf_rn(-py, dL, w[1]) * iL;
+    float du, dv;
+    if (pz >= 0.0f) {
+        du = dpx;
+        dv = dpy;
+    } else {  // u = (1 - |p_y|) s(p_x), v = (1 - |p_x|) s(p_y)
+        float s = sgnp(px) * sgnp(py);
+        du = -s * dpy;
+        dv = -s * dpx;
+    }
+    float u, v;
+    oct_encode(q[0], q[1], q[2], u, v);
+    int idx[4];
+    float wt[4];
+    bilinear_taps(u, v, g.N, idx, wt);
+    float fx = wt[1] + wt[3], fy = wt[2] + wt[3];  // fractional position between the tap centres
+    float dx = 0.5f * (float)g.N * du, dy = 0.5f * (float)g.N * dv;
+    float dw[4] = {-dx * (1.0f - fy) - (1.0f - fx) * dy, dx * (1.0f - fy) - fx * dy, (1.0f - fx) * dy - dx * fy,
+                   dx * fy + fx * dy};
+    const uint16_t *R = rad + (int64_t)r.probe * g.N * g.N * 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint16_t *px3 = R + 3 * idx[k];
+        drgb[0] = __fmaf_rn(dw[k], half_bits(px3[0]), drgb[0]);
+        drgb[1] = __fmaf_rn(dw[k], half_bits(px3[1]), drgb[1]);
+        drgb[2] = __fmaf_rn(dw[k], half_bits(px3[2]), drgb[2]);
+    }
 }
 
 // Radiance of a HIT from its taps; also returns the taps for the adjoint.
