@@ -236,7 +236,7 @@ def large(pt, synth, torch, np, steps=3):
     hit_frac = float((st == 1).mean())
     gr = torch.ones((rays, 3), device="cuda")
     g = torch.zeros((P, N, N, 3), device="cuda")
-    bopts = pt.trace_opts(tile=(4, 16), start_level=3)
+    bopts = pt.trace_opts(tile=(4, 16), start_level=3)  # 8 views: one persistent adjoint launch
     pt.probe_trace_backward(grid, va, gr, g, bopts)
     torch.cuda.synchronize()
     e0.record()

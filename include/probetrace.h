@@ -195,8 +195,8 @@ pt_status probe_trace_rays(const pt_grid *grid, const uint16_t *radiance_dev, co
  *   grad_rgb_dev       [rays][3] FP32, same ray order as probe_trace
  *   grad_radiance_dev  [P][N][N][3] FP32, ACCUMULATED into (+=); caller zeroes it
  * Summation order depends on scheduling (FP32 atomics after an in-wavefront reduction).
- * opts->flags PT_FLAG_PERSISTENT or PT_FLAG_GRAPH: one persistent launch over the tiles of
- * all views (not captured in a graph); otherwise one launch per view.  With
+ * More than one view, or opts->flags PT_FLAG_PERSISTENT or PT_FLAG_GRAPH: one persistent
+ * launch over the tiles of all views (not captured in a graph); otherwise one launch.  With
  * PT_FLAG_NEAREST the single tap is the hit texel.  A grid's calls are stream-ordered
  * state (view tables, tile counter): do not run two calls on one grid concurrently on
  * different streams.  Errors: INVALID_ARGUMENT, HIP. */

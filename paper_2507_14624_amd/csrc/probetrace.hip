@@ -935,9 +935,10 @@ static pt_status launch_adjoint(const pt_grid *g, const pt_view *views_host, int
         if (st != PT_OK) return st;
     }
     uint32_t flags = opts ? opts->flags : 0;
-    if (flags & (PT_FLAG_PERSISTENT | PT_FLAG_GRAPH)) {
+    if ((flags & (PT_FLAG_PERSISTENT | PT_FLAG_GRAPH)) || n_views > 1) {
         // one persistent launch over the tiles of all views (the graph flag means the same
-        // here: the adjoint is not captured)
+        // here: the adjoint is not captured).  Always for more than one view: one launch per
+        // view measured 2.3x (8 views of 3840x2160) to 3.3x (32 of 512x512) slower.
         st = upload_views(mg, vd, s);
         if (st != PT_OK) return st;
         launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
