@@ -300,14 +300,6 @@ __device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *_
     }
 }
 
-// Workgroup -> tile order that keeps neighbouring tiles on one XCD: workgroups are handed
-// to the 8 XCDs round-robin, so XCD x receives workgroups x, x+8, ...; give it one
-// contiguous run of tiles instead.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    int q = nb >> 3, rem = nb & 7;
-    int x = b & 7, slot = b >> 3;
-    return x * q + min(x, rem) + slot;
-}
 
 // Cage order of every cell for every view (the eye is the same for all rays of a view).
 __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single, int n_views, int cells,
@@ -330,8 +322,10 @@ PT_TRACE_KERNEL k_trace_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__
                              const uint32_t *__restrict__ ccage, const uint16_t *__restrict__ rad, Outputs o, int tw,
                              int th) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int nb = gridDim.x;
-    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
+    // workgroups in launch order: consecutive tiles go to different XCDs (the hardware hands
+    // workgroups out round-robin), which spreads a costly region of the image over all of
+    // them (keeping each XCD on a contiguous run of tiles was 8-9% slower)
+    int tile = blockIdx.x * 4 + wave;
     int tiles_y = (v.H + th - 1) / th;
     if (tile >= v.tiles_x * tiles_y) return;
     int x = (tile % v.tiles_x) * tw + lane % tw;
@@ -546,8 +540,10 @@ template <bool W, int T, bool Geo>
 PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__restrict__ cage,
                                 const uint32_t *__restrict__ ccage, AdjointIO io, int tw, int th) {
     int wave = threadIdx.x >> 6;
-    int nb = gridDim.x;
-    int tile = xcd_tile(blockIdx.x, nb) * 4 + wave;
+    // workgroups in launch order: consecutive tiles go to different XCDs (the hardware hands
+    // workgroups out round-robin), which spreads a costly region of the image over all of
+    // them (keeping each XCD on a contiguous run of tiles was 8-9% slower)
+    int tile = blockIdx.x * 4 + wave;
     int tiles_y = (v.H + th - 1) / th;
     if (tile >= v.tiles_x * tiles_y) return;  // whole wavefronts only
     backward_tile<W, T, Geo>(g, L2, v, tile, cage, ccage, io, tw, th);
