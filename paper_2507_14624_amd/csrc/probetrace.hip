@@ -1016,12 +1016,26 @@ extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_d
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    float best = INFINITY;
-    pt_trace_opts bo = *opts;
     Outputs o{rgb_dev, nullptr, nullptr, nullptr};
     pt_status st = PT_OK;
+    // average time of `reps` back-to-back launches of candidate c, after one warm-up
+    auto time_of = [&](const pt_trace_opts &c, int reps, float &ms) -> pt_status {
+        pt_status r = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
+        if (r != PT_OK) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(PT_ERR_HIP, "hipEventRecord");
+        for (int k = 0; k < reps && r == PT_OK; ++k) r = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
+        if (r != PT_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(PT_ERR_HIP, "autotune timing");
+        ms /= (float)reps;
+        return PT_OK;
+    };
     // candidates: tile shape x pyramid start level x (per-view launches | one persistent
-    // launch); the graph flag, if set by the caller, is kept
+    // launch); the graph flag, if set by the caller, is kept.  A sweep of 8 launches each,
+    // then the 3 fastest again, interleaved, 3 rounds of 8 (run-to-run noise is ~2%, about
+    // the spread between the best candidates).
+    std::vector<std::pair<float, pt_trace_opts>> cand;
     for (auto &sh : shapes) {
         for (int lv = g->L - 1; lv >= std::max(0, g->L - 3) && st == PT_OK; --lv) {
             for (int persistent = 0; persistent < 2 && st == PT_OK; ++persistent) {
@@ -1031,23 +1045,27 @@ extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_d
                 c.start_level = lv;
                 c.flags = (opts->flags & ~PT_FLAG_PERSISTENT) | (persistent ? PT_FLAG_PERSISTENT : 0u);
                 if (c.flags & PT_FLAG_GRAPH) c.flags &= ~PT_FLAG_PERSISTENT;  // the graph is persistent
-                st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);  // warm-up
-                if (st != PT_OK) break;
-                if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PT_ERR_HIP, "hipEventRecord"); break; }
-                for (int r = 0; r < 3 && st == PT_OK; ++r) st = trace_impl(g, radiance_dev, views_host, n_views, o, &c, s);
-                if (st != PT_OK) break;
                 float ms = 0;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                    st = fail(PT_ERR_HIP, "autotune timing");
-                    break;
-                }
-                if (ms < best) {
-                    best = ms;
-                    bo = c;
-                }
+                st = time_of(c, 8, ms);
+                if (st == PT_OK) cand.push_back({ms, c});
             }
         }
+    }
+    pt_trace_opts bo = *opts;
+    if (st == PT_OK && !cand.empty()) {
+        std::sort(cand.begin(), cand.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        size_t top = std::min<size_t>(3, cand.size());
+        std::vector<float> tot(top, 0.0f);
+        for (int round = 0; round < 3 && st == PT_OK; ++round)
+            for (size_t i = 0; i < top && st == PT_OK; ++i) {
+                float ms = 0;
+                st = time_of(cand[i].second, 8, ms);
+                tot[i] += ms;
+            }
+        size_t bi = 0;
+        for (size_t i = 1; i < top; ++i)
+            if (tot[i] < tot[bi]) bi = i;
+        bo = cand[bi].second;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
