@@ -423,16 +423,19 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         float rs2 = rho2_at(Xp, w, s.ts);
         int top = g.top;
         if (!miss) {
-            int fxe = (int)floorf(xe), fye = (int)floorf(ye);
             // O(1) MISS test of the whole piece: its projection is a straight segment, so the
-            // texels it crosses lie in the box spanned by its end texels (widened by one texel
-            // against rounding).  At the pyramid level where that box spans at most 2x2
-            // texels, if their minimum stored distance is not below the piece's largest radial
-            // distance (at an end: rho is convex) with a 2^-16 slack, no texel can fire.
-            int bi0 = min(max(min(fxs, fxe) - 1, s.ilo), s.ihi);
-            int bi1 = min(max(max(fxs, fxe) + 1, s.ilo), s.ihi);
-            int bj0 = min(max(min(fys, fye) - 1, s.jlo), s.jhi);
-            int bj1 = min(max(max(fys, fye) + 1, s.jlo), s.jhi);
+            // texels it crosses lie in the box spanned by its end points.  The box is widened
+            // by N 2^-16 texels (2^-16 of the coordinate range, hundreds of ulps of the FP32
+            // end points and of the march's crossings), so an end point within rounding of a
+            // texel boundary also takes the texel beyond it.  At the pyramid level where that
+            // box spans at most 2x2 texels, if their minimum stored distance is not below the
+            // piece's largest radial distance (at an end: rho is convex) with a 2^-16 slack,
+            // no texel can fire.
+            const float eps = (float)N * 0x1p-16f;
+            int bi0 = min(max((int)floorf(fminf(xs, xe) - eps), s.ilo), s.ihi);
+            int bi1 = min(max((int)floorf(fmaxf(xs, xe) + eps), s.ilo), s.ihi);
+            int bj0 = min(max((int)floorf(fminf(ys, ye) - eps), s.jlo), s.jhi);
+            int bj1 = min(max((int)floorf(fmaxf(ys, ye) + eps), s.jlo), s.jhi);
             // smallest level where the box spans at most 2 texels per axis: a difference
             // below 2^(b+1) spans at most 2 texels at level b or b+1 (b = bit length - 1)
             int lv = 31 - __builtin_clz((unsigned)max(max(bi1 - bi0, bj1 - bj0), 1));
