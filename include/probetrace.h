@@ -15,7 +15,8 @@
  *     MIN pyramid (so the hierarchy only skips space, never changes a result);
  *   - a camera ray walks the grid cells it crosses (Ray Trace Using Multiple Probes >
  *     Grid Iterator) and, in each cell, tries the cell's 8 corner probes closest to the
- *     eye first, falling through on MISS and on UNKNOWN (Less Than 8 Probes);
+ *     eye first, falling through on MISS and on UNKNOWN (Less Than 8 Probes); a layout of
+ *     fewer than 8 probes has no cells: every probe, closest first, over the whole ray;
  *   - one probe: if the eye sits at the probe, an O(1) lookup of the map at oct(w)
  *     (Eye Aligned with a Probe, appendix traceOneProbe); otherwise the ray is split
  *     into at most four straight pieces of the octahedral map and each is marched,
