@@ -94,7 +94,37 @@ def cpu_baseline(probes, view):
                        f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()),
                 one_thread={"value": len(o[::8]) / dt1 / 1e6, "unit": "Mrays/s",
                             "sample": f"every 8th ray of the frame ({len(o[::8])} rays), {dt1:.1f} s"},
-                cpu_model=model, nproc=os.cpu_count())
+                cpu_model=model, nproc=os.cpu_count(), other_workloads=cpu_other_workloads(threads))
+
+
+def cpu_other_workloads(threads):
+    """The oracle on the other workloads, on bounded samples: the tiny room in full, the
+    batched walk on its first 4 views, the differentiable grid's forward and radiance
+    VJP on 2 of its views."""
+    import numpy as np
+    import oracle
+    import synth
+    out = {}
+
+    def rays_of(views):
+        parts = [oracle.view_rays(*v.as_tuple()) for v in views]
+        return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+    for name, nv, vjp in (("tiny", 1, False), ("batched", 4, False), ("diff", 2, True)):
+        scene, probes, views = synth.workload(name, nthreads=threads)
+        g = oracle.Grid.from_probes(probes)
+        o, d = rays_of(views[:nv])
+        t0 = time.perf_counter()
+        r = oracle.trace(g, o, d, nthreads=threads)
+        dt = time.perf_counter() - t0
+        e = {"value": round(len(o) / dt / 1e6, 4), "unit": "Mrays/s", "rays": len(o), "s": round(dt, 2)}
+        if vjp:
+            t1 = time.perf_counter()
+            oracle.vjp(g, r, np.ones((len(o), 3)))
+            e["vjp_s"] = round(time.perf_counter() - t1, 2)
+        out[name] = e
+        del g
+    return out
 
 
 def differentiable(pt, synth, torch, np, steps=5):
@@ -390,7 +420,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(probes, view)
-        cb["one_thread"]["value"] = round(cb["one_thread"]["value"], 4)
+        cb["one_thread"]["value"] = round(cb["one_thread"]["value"], 4)  # other_workloads are rounded already
         result["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(result), flush=True)
 
