@@ -390,7 +390,19 @@ def main():
         print("[bench] timing forward+backward", file=sys.stderr, flush=True)
         ms_fb, _ = time_steps(fwd_bwd, max(3, args.steps // 2), 1, torch)
         result["fwd_bwd"] = {"value": round(rays / (ms_fb * 1e-3) / 1e6, 3), "unit": "Mrays/s",
-                             "ms_per_step": round(ms_fb, 4)}
+                             "ms_per_step": round(ms_fb, 4), "adjoint": "recomputes the trace"}
+        # the same step with the adjoint from the forward's stored hits (probe, texel, t)
+        hout = (out[0], torch.empty(rays, device="cuda"), None, torch.empty((rays, 2), dtype=torch.int32, device="cuda"))
+
+        def fwd_bwd_hits():
+            pt.probe_trace(grid, rad, va, opts, out=hout)
+            grad.zero_()
+            pt.probe_trace_backward_hits(grid, va, hout[3], hout[1], gout, grad, opts)
+
+        ms_fh, _ = time_steps(fwd_bwd_hits, max(3, args.steps // 2), 1, torch)
+        result["fwd_bwd_stored_hits"] = {"value": round(rays / (ms_fh * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                                         "ms_per_step": round(ms_fh, 4),
+                                         "adjoint": "from the forward's hit and t outputs (8 B/ray kept)"}
         print("[bench] batched workload", file=sys.stderr, flush=True)
         _, _, bviews = synth.workload("batched")
         bva = pt.make_views(bviews)

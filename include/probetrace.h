@@ -205,6 +205,17 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
                                const float *grad_rgb_dev, float *grad_radiance_dev, const pt_trace_opts *opts,
                                void *stream);
 
+/* The same adjoint from the forward's own outputs instead of a recomputed trace, for
+ * callers that kept them: hit_dev ([rays][2] int32, (probe, texel) or (-1, -1)) and t_dev
+ * ([rays] FP32) exactly as probe_trace wrote them for these views and this grid.  The
+ * sample direction of each HIT is rebuilt from (probe, t) with the forward's operations, so
+ * the result equals probe_trace_backward's up to the order of the FP32 atomics; the march
+ * is not repeated (8 bytes per ray of storage against a second trace).  One launch over the
+ * rays of all views.  Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace_backward_hits(const pt_grid *grid, const pt_view *views_host, int32_t n_views,
+                                   const int32_t *hit_dev, const float *t_dev, const float *grad_rgb_dev,
+                                   float *grad_radiance_dev, const pt_trace_opts *opts, void *stream);
+
 /* Adjoint of probe_trace with respect to the stored distances (gradients through geometry;
  * an extension beyond the paper, which renders forward only), the classification held
  * fixed: which probe and texel a ray hits, and whether it is HIT, do not move.  A HIT ray

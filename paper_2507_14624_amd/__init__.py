@@ -26,8 +26,8 @@ PT_FLAG_WIDE = 8
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",
-            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_distance",
-            "probe_autotune", "pt_last_error")
+            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_hits",
+            "probe_trace_backward_distance", "probe_autotune", "pt_last_error")
 
 
 class PtGridDesc(ctypes.Structure):
@@ -80,9 +80,12 @@ def load_library(path: str = LIB_PATH):
     lib.probe_trace_backward_distance.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp,
                                                   ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_grid_set_distance.argtypes = [vp, vp, vp]
+    lib.probe_trace_backward_hits.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp,
+                                              ctypes.POINTER(PtTraceOpts), vp]
     for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
                  "probe_trace", "probe_trace_rays", "probe_grid_set_distance",
-                 "probe_trace_backward", "probe_trace_backward_distance", "probe_autotune"):
+                 "probe_trace_backward", "probe_trace_backward_hits", "probe_trace_backward_distance",
+                 "probe_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
     lib.pt_last_error.restype = ctypes.c_char_p
@@ -324,6 +327,27 @@ def probe_trace_backward(grid: ProbeGrid, views, grad_rgb, grad_radiance, opts: 
     return grad_radiance
 
 
+def probe_trace_backward_hits(grid: ProbeGrid, views, hit, t, grad_rgb, grad_radiance,
+                              opts: PtTraceOpts | None = None, stream=None):
+    """probe_trace_backward from the forward's hit [rays,2] int32 and t [rays] outputs (no
+    recomputed march); accumulates (+=) into grad_radiance [P_total,N,N,3] FP32."""
+    lib = load_library()
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    hit = _dev_tensor(hit, torch.int32, "hit")
+    t = _dev_tensor(t, torch.float32, "t")
+    grad_rgb = _dev_tensor(grad_rgb, torch.float32, "grad_rgb")
+    grad_radiance = _dev_tensor(grad_radiance, torch.float32, "grad_radiance")
+    _need(hit, 2 * rays, "hit")
+    _need(t, rays, "t")
+    _need(grad_rgb, 3 * rays, "grad_rgb")
+    _need(grad_radiance, grid.P_total * grid.N * grid.N * 3, "grad_radiance")
+    _check(lib.probe_trace_backward_hits(grid.handle, va, len(va), _ptr(hit), _ptr(t), _ptr(grad_rgb),
+                                         _ptr(grad_radiance), ctypes.byref(opts) if opts is not None else None,
+                                         _stream(stream)))
+    return grad_radiance
+
+
 def probe_trace_backward_distance(grid: ProbeGrid, radiance_half, views, grad_rgb, grad_t, grad_distance,
                                   opts: PtTraceOpts | None = None, stream=None):
     """Accumulate (+=) the gradient of sum(grad_rgb * rgb) + sum(grad_t * t) with respect to
@@ -368,22 +392,28 @@ class ProbeTraceFn(torch.autograd.Function):
 
     forward: the FP32 master radiance is rounded to the FP16 storage the trace reads;
     backward: probe_trace_backward into a zeroed FP32 buffer, passed straight through the
-    FP16 rounding to the master."""
+    FP16 rounding to the master.  keep_hits=True keeps the forward's hit and t outputs (8
+    bytes per ray) and runs probe_trace_backward_hits instead of recomputing the trace."""
 
     @staticmethod
-    def forward(ctx, master, grid, views, opts=None):
+    def forward(ctx, master, grid, views, opts=None, keep_hits=False):
         storage = master.detach().to(torch.float16).contiguous()
         va = views if isinstance(views, ctypes.Array) else make_views(views)
-        res = probe_trace(grid, storage, va, opts, want_t=False, want_status=False, want_hit=False)
+        res = probe_trace(grid, storage, va, opts, want_t=keep_hits, want_status=False, want_hit=keep_hits)
         ctx.grid, ctx.views, ctx.opts = grid, va, opts
         ctx.shape = master.shape
+        ctx.hits = (res["hit"], res["t"]) if keep_hits else None
         return res["rgb"]
 
     @staticmethod
     def backward(ctx, grad_rgb):
         g = torch.zeros(ctx.shape, dtype=torch.float32, device=grad_rgb.device)
-        probe_trace_backward(ctx.grid, ctx.views, grad_rgb.contiguous().float(), g, ctx.opts)
-        return g, None, None, None
+        if ctx.hits is not None:
+            probe_trace_backward_hits(ctx.grid, ctx.views, ctx.hits[0], ctx.hits[1], grad_rgb.contiguous().float(), g,
+                                      ctx.opts)
+        else:
+            probe_trace_backward(ctx.grid, ctx.views, grad_rgb.contiguous().float(), g, ctx.opts)
+        return g, None, None, None, None
 
 
 

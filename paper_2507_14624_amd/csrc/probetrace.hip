@@ -549,6 +549,66 @@ PT_TRACE_KERNEL k_backward_view(GridDev g, Level2 L2, ViewDev v, const uint32_t 
     backward_tile<W, T, Geo>(g, L2, v, tile, cage, ccage, io, tw, th);
 }
 
+// Radiance adjoint from the forward's own outputs instead of a recomputed trace: the HIT
+// probe and texel (hit) and hit distance (tt) that probe_trace wrote for every ray.  The
+// sample direction is rebuilt from them with the forward's operations (the eye lookup's
+// test, X - O + t w), so taps and weights equal the recompute adjoint's bit for bit; only
+// the march is skipped.  One ray per lane over the rays of all views (consecutive rays of
+// a row share a wavefront, so the segmented scatter still merges their taps).
+template <int T>
+__global__ void __launch_bounds__(256) k_backward_hits(GridDev g, Level2 L2, const ViewDev *__restrict__ views,
+                                                       int n_views, int64_t rays, const int32_t *__restrict__ hit,
+                                                       const float *__restrict__ tt,
+                                                       const float *__restrict__ grad_rgb,
+                                                       float *__restrict__ grad_rad) {
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t key[4] = {-1, -1, -1, -1};
+    float val[4][3] = {};
+    int p = ray < rays ? hit[2 * ray] : -1;
+    if (p >= 0) {
+        // view holding this ray (views are in output order)
+        int lo = 0, hi = n_views - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (views[mid].ray_offset <= ray) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewDev &v = views[lo];
+        int local = (int)(ray - v.ray_offset);
+        int y = local / v.W, x = local - y * v.W;
+        float w[3];
+        camera_ray(v, x, y, w);
+        const bool coarse = T == kTwoLevel && p >= L2.Pf;
+        const GridDev &G = coarse ? L2.c : g;
+        int pl = coarse ? p - L2.Pf : p;
+        int pc[3] = {pl % G.n[0], (pl / G.n[0]) % G.n[1], pl / (G.n[0] * G.n[1])};
+        float Xp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Xp[a] = v.pos[a] - grid_coord(G, a, pc[a]);
+        RayResult r;
+        r.status = ST_HIT;
+        r.probe = p;
+        r.texel = hit[2 * ray + 1];
+        r.t = tt[ray];
+        r.eye = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0])) <= G.eye_eps2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.q[a] = r.eye ? w[a] : __fmaf_rn(r.t, w[a], Xp[a]);
+        float gr[3] = {grad_rgb[3 * ray], grad_rgb[3 * ray + 1], grad_rgb[3 * ray + 2]};
+        int idx[4];
+        float wt[4];
+        hit_taps(g, r, idx, wt);
+        int64_t base = (int64_t)p * g.N * g.N;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (wt[k] != 0.0f) key[k] = 3 * (base + idx[k]);
+            val[k][0] = wt[k] * gr[0];
+            val[k][1] = wt[k] * gr[1];
+            val[k][2] = wt[k] * gr[2];
+        }
+    }
+    wave_scatter_add(grad_rad, key, val);
+}
+
 // Persistent adjoint over many views: wavefronts pop tiles of all views from a device
 // counter (views sorted by tile_begin) until the queue is empty.
 template <bool W, int T, bool Geo>
@@ -971,6 +1031,38 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
     AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev};
     return launch_adjoint<false>(g, views_host, n_views, io, opts, stream);
+}
+
+extern "C" pt_status probe_trace_backward_hits(const pt_grid *g, const pt_view *views_host, int32_t n_views,
+                                               const int32_t *hit_dev, const float *t_dev,
+                                               const float *grad_rgb_dev, float *grad_radiance_dev,
+                                               const pt_trace_opts *opts, void *stream) {
+    if (!g || !hit_dev || !t_dev || !grad_rgb_dev || !grad_radiance_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward_hits: NULL argument");
+    int tw, th;
+    pt_status st = tile_shape(opts, tw, th);
+    if (st != PT_OK) return st;
+    std::vector<ViewDev> vd;
+    int64_t rays;
+    int tiles;
+    st = check_views(views_host, n_views, tw, th, vd, rays, tiles);
+    if (st != PT_OK) return st;
+    if (rays == 0) return PT_OK;
+    TraceCtx c;
+    make_ctx(g, opts, c);
+    hipStream_t s = (hipStream_t)stream;
+    pt_grid *mg = const_cast<pt_grid *>(g);
+    st = upload_views(mg, vd, s);
+    if (st != PT_OK) return st;
+    unsigned nb = blocks_for(rays, 256);
+    if (c.two)
+        hipLaunchKernelGGL(k_backward_hits<kTwoLevel>, dim3(nb), dim3(256), 0, s, c.d, c.L2, mg->views_dev, n_views,
+                           rays, hit_dev, t_dev, grad_rgb_dev, grad_radiance_dev);
+    else
+        hipLaunchKernelGGL(k_backward_hits<kGrid>, dim3(nb), dim3(256), 0, s, c.d, c.L2, mg->views_dev, n_views, rays,
+                           hit_dev, t_dev, grad_rgb_dev, grad_radiance_dev);
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
 }
 
 extern "C" pt_status probe_trace_backward_distance(const pt_grid *g, const uint16_t *radiance_dev,

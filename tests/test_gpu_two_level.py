@@ -126,6 +126,11 @@ def test_two_level_backward_matches_oracle_vjp():
     gp = torch.zeros_like(gg)
     pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gp, pt.trace_opts(flags=pt.PT_FLAG_PERSISTENT))
     torch.testing.assert_close(gp, gg, rtol=1e-5, atol=1e-6)
+    # and so does the adjoint from the forward's stored hits (coarse probes included)
+    r2 = pt.probe_trace(grid, rad, views)
+    gh = torch.zeros_like(gg)
+    pt.probe_trace_backward_hits(grid, views, r2["hit"], r2["t"], torch.from_numpy(g).cuda(), gh)
+    torch.testing.assert_close(gh, gg, rtol=1e-5, atol=1e-6)
     ref = oracle.vjp((og, cg), orc, g.astype(np.float64))
     wabs = oracle.vjp((og, cg), orc, np.abs(g).astype(np.float64))
     unit = dict(orc)
