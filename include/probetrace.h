@@ -185,7 +185,9 @@ pt_status probe_trace(const pt_grid *grid, const uint16_t *radiance_dev, const p
                       void *stream);
 
 /* Trace arbitrary rays: origins_dev and dirs_dev are [n][3] FP32 (directions need not be
- * unit length; zero-length directions give MISS).  Outputs as for probe_trace. */
+ * unit length; zero-length directions give MISS).  Outputs as for probe_trace.  n = 0
+ * returns PT_OK at once and touches nothing (the buffers may then be NULL); n < 0 is
+ * INVALID_ARGUMENT. */
 pt_status probe_trace_rays(const pt_grid *grid, const uint16_t *radiance_dev, const float *origins_dev,
                            const float *dirs_dev, int64_t n, float *rgb_dev, float *t_dev, uint8_t *status_dev,
                            int32_t *hit_dev, const pt_trace_opts *opts, void *stream);

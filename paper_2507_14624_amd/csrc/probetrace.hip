@@ -951,10 +951,11 @@ extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance
                                       const float *dirs_dev, int64_t n, float *rgb_dev, float *t_dev,
                                       uint8_t *status_dev, int32_t *hit_dev, const pt_trace_opts *opts,
                                       void *stream) {
-    if (!g || !radiance_dev || !origins_dev || !dirs_dev || !rgb_dev)
-        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: NULL argument");
+    if (!g) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: NULL argument");
     if (n < 0) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: n < 0");
-    if (n == 0) return PT_OK;
+    if (n == 0) return PT_OK;  // nothing to read or write: the buffers may be NULL
+    if (!radiance_dev || !origins_dev || !dirs_dev || !rgb_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_rays: NULL argument");
     TraceCtx c;
     make_ctx(g, opts, c);
     Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
