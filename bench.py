@@ -139,20 +139,27 @@ def differentiable(pt, synth, torch, np, steps=5):
     target = pt.probe_trace(grid, trad, views, want_t=False, want_status=False, want_hit=False)["rgb"]
     del trad
     rays = pt.n_rays(views)
-    fit = RadianceFit(grid, views, target)
-    for _ in range(3):  # warm-up on a throw-away fit
-        fit.step()
-    del fit
-    fit = RadianceFit(grid, views, target)  # the timed run starts from the initial radiance
-    losses = [fit.step().item()]
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    out = [fit.step() for _ in range(steps)]
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    losses += [x.item() for x in out]
+
+    def timed_fit(keep_hits):
+        fit = RadianceFit(grid, views, target, keep_hits=keep_hits)
+        for _ in range(3):  # warm-up on a throw-away fit
+            fit.step()
+        del fit
+        fit = RadianceFit(grid, views, target, keep_hits=keep_hits)  # timed from the initial radiance
+        losses = [fit.step().item()]
+        torch.cuda.synchronize()
+        e0.record()
+        out = [fit.step() for _ in range(steps)]
+        e1.record()
+        torch.cuda.synchronize()
+        return fit, e0.elapsed_time(e1) / steps, losses + [x.item() for x in out]
+
+    # the default adjoint from the forward's stored hits (no second trace), then the
+    # recomputing adjoint
+    fit, ms_sh, losses_sh = timed_fit(True)
+    del fit
+    fit, ms, losses = timed_fit(False)
     # the trace kernels alone in one step: forward and backward
     va = pt.make_views(views)
     g = torch.zeros((grid.P, grid.N, grid.N, 3), device="cuda")
@@ -166,6 +173,16 @@ def differentiable(pt, synth, torch, np, steps=5):
     e1.record()
     torch.cuda.synchronize()
     ms_fb = e0.elapsed_time(e1) / steps
+    hout = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"), None,
+            torch.empty((rays, 2), dtype=torch.int32, device="cuda"))
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, storage, va, po, out=hout)
+        pt.probe_trace_backward_hits(grid, va, hout[3], hout[1], gr, g, po)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fh = e0.elapsed_time(e1) / steps
+    del hout
     # gradient through the stored distances: forward (rgb and t) + distance adjoint
     del g
     gd = torch.zeros((grid.P, grid.N, grid.N), device="cuda")
@@ -180,13 +197,19 @@ def differentiable(pt, synth, torch, np, steps=5):
     ms_geo = e0.elapsed_time(e1) / steps
     return {"workload": "16x16x8 probes, 256^2 maps (6 levels), 32 views of 512x512; FP32 master, FP16 storage; "
                         "Adam lr 1e-2 from 0.5",
-            "rays_per_step": rays, "adam_step_ms": round(ms, 3),
-            "adam_step_mrays_s": round(rays / (ms * 1e-3) / 1e6, 2),
-            "fwd_bwd_kernels_ms": round(ms_fb, 3), "fwd_bwd_mrays_s": round(rays / (ms_fb * 1e-3) / 1e6, 2),
+            "rays_per_step": rays, "adam_step_ms": round(ms_sh, 3),
+            "adam_step_mrays_s": round(rays / (ms_sh * 1e-3) / 1e6, 2),
+            "fwd_bwd_kernels_ms": round(ms_fh, 3), "fwd_bwd_mrays_s": round(rays / (ms_fh * 1e-3) / 1e6, 2),
+            "adjoint": "from the forward's hit and t outputs (8 B/ray kept), no second trace",
+            "recompute": {"adam_step_ms": round(ms, 3), "adam_step_mrays_s": round(rays / (ms * 1e-3) / 1e6, 2),
+                          "fwd_bwd_kernels_ms": round(ms_fb, 3),
+                          "fwd_bwd_mrays_s": round(rays / (ms_fb * 1e-3) / 1e6, 2),
+                          "loss": [round(x, 6) for x in losses],
+                          "adjoint": "recomputes the trace"},
             "launch": "one persistent launch over the 32 views, forward and adjoint",
             "geometry_fwd_bwd_kernels_ms": round(ms_geo, 3),
             "geometry_fwd_bwd_mrays_s": round(rays / (ms_geo * 1e-3) / 1e6, 2),
-            "loss": [round(x, 6) for x in losses]}
+            "loss": [round(x, 6) for x in losses_sh]}
 
 
 def bake(pt, synth, torch, np, n_points=4_000_000, steps=5):
@@ -276,6 +299,16 @@ def large(pt, synth, torch, np, steps=3):
     e1.record()
     torch.cuda.synchronize()
     ms_fb = e0.elapsed_time(e1) / steps
+    hout = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"), None,
+            torch.empty((rays, 2), dtype=torch.int32, device="cuda"))
+    e0.record()
+    for _ in range(steps):
+        pt.probe_trace(grid, storage, va, po, out=hout)
+        pt.probe_trace_backward_hits(grid, va, hout[3], hout[1], gr, g, po)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fh = e0.elapsed_time(e1) / steps
+    del hout
     return {"workload": f"city block of {n_boxes} boxes; fine 64x64x16 + coarse 16x16x4 probes (coarse planes = every "
                         f"4th fine plane), 128^2 maps, 5-level pyramids, {P} probes ({dead:.0%} inside buildings, "
                         f"D = 0); 8 views of 3840x2160", "rays": rays, "hbm_probe_bytes": int(P * N * N * (8 + 4 + 6)),

@@ -213,7 +213,8 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
  * sample direction of each HIT is rebuilt from (probe, t) with the forward's operations, so
  * the result equals probe_trace_backward's up to the order of the FP32 atomics; the march
  * is not repeated (8 bytes per ray of storage against a second trace).  One launch over the
- * rays of all views.  Errors: INVALID_ARGUMENT, HIP. */
+ * pixel tiles of all views, one tile of opts' tile shape per wavefront.  Errors:
+ * INVALID_ARGUMENT (NULL buffers, bad views or tile shape), HIP. */
 pt_status probe_trace_backward_hits(const pt_grid *grid, const pt_view *views_host, int32_t n_views,
                                    const int32_t *hit_dev, const float *t_dev, const float *grad_rgb_dev,
                                    float *grad_radiance_dev, const pt_trace_opts *opts, void *stream);

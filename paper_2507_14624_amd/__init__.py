@@ -416,7 +416,6 @@ class ProbeTraceFn(torch.autograd.Function):
         return g, None, None, None, None
 
 
-
 class ProbeGeometryFn(torch.autograd.Function):
     """(rgb, t) = trace(distance, radiance) of a single-level grid, with the classification
     held fixed in the backward.

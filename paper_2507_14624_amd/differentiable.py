@@ -15,7 +15,7 @@ from . import PT_FLAG_PERSISTENT, ProbeTraceFn, make_views, trace_opts
 class RadianceFit:
     """Adam on FP32 master radiance [P,N,N,3] against target images of the given views."""
 
-    def __init__(self, grid, views, target_rgb, init=0.5, lr=1e-2, opts=None, keep_hits=False):
+    def __init__(self, grid, views, target_rgb, init=0.5, lr=1e-2, opts=None, keep_hits=True):
         self.grid = grid
         self.views = make_views(views)
         if opts is None and len(self.views) > 1:
@@ -31,7 +31,8 @@ class RadianceFit:
         except (RuntimeError, TypeError, ValueError):
             self.optim = torch.optim.Adam([self.master], lr=lr)
         self.opts = opts
-        self.keep_hits = keep_hits  # adjoint from the forward's hits instead of a recomputed trace
+        # adjoint from the forward's hits (8 bytes per ray) instead of a recomputed trace
+        self.keep_hits = keep_hits
 
     def loss(self):
         rgb = ProbeTraceFn.apply(self.master, self.grid, self.views, self.opts, self.keep_hits)
