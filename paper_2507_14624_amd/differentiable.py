@@ -2,7 +2,7 @@
 
 The trace is linear in the stored radiance once the hit test is fixed, so an image loss
 can be minimised over the radiance texels with its exact gradient (ProbeTraceFn ->
-probe_trace_backward).  The master radiance is FP32 and is rounded to the FP16 storage
+probe_trace_backward_hits from the forward's stored hits, or probe_trace_backward).  The master radiance is FP32 and is rounded to the FP16 storage
 the trace reads on every forward; Adam (torch) updates the master.
 """
 from __future__ import annotations
@@ -40,7 +40,9 @@ class RadianceFit:
 
     def step(self) -> torch.Tensor:
         """One Adam step; returns the loss before the update (device scalar)."""
-        self.optim.zero_grad(set_to_none=False)
+        # no gradient held between steps: the adjoint's fresh buffer becomes the gradient
+        # itself (zeroing a held one and adding into it would move 6.4 GB more per step)
+        self.optim.zero_grad(set_to_none=True)
         loss = self.loss()
         loss.backward()
         self.optim.step()

@@ -36,8 +36,8 @@ def _check_grad(pt, probes, grid, rad, views, seed=0, nearest=False, flags=0):
     og = oracle.Grid.from_probes(probes)
     flags |= pt.PT_FLAG_NEAREST if nearest else 0
     opts = pt.trace_opts(flags=flags) if flags else None
-    res = pt.probe_trace(grid, rad, views, opts)
-    res = {k: v.cpu().numpy() for k, v in res.items()}
+    dev = pt.probe_trace(grid, rad, views, opts)
+    res = {k: v.cpu().numpy() for k, v in dev.items()}
     o_parts, d_parts = [], []
     for v in views:
         o, d = oracle.view_rays(*v.as_tuple())
@@ -58,11 +58,15 @@ def _check_grad(pt, probes, grid, rad, views, seed=0, nearest=False, flags=0):
     unit["wts"] = (orc["wts"] != 0).astype(np.float64)
     gabs = oracle.vjp(og, unit, np.abs(g).astype(np.float64))
     tol = 1e-5 * wabs + 1e-3 * gabs + 1e-8
-    err = np.abs(got - ref)
-    bad = err > tol
-    print(f"[grad] n={s['n']} disagree={s['disagree']} max_err={err.max():.3e} "
-          f"max_err/tol={(err / tol).max():.3f} nonzero={np.count_nonzero(ref)}", flush=True)
-    assert not bad.any(), np.argwhere(bad)[:10]
+    # the same adjoint from the forward's stored (probe, texel) and t
+    gh = torch.zeros_like(gg)
+    pt.probe_trace_backward_hits(grid, views, dev["hit"], dev["t"], torch.from_numpy(g).cuda(), gh, opts)
+    for label, x in (("recompute", got), ("stored hits", gh.cpu().numpy().astype(np.float64))):
+        err = np.abs(x - ref)
+        bad = err > tol
+        print(f"[grad {label}] n={s['n']} disagree={s['disagree']} max_err={err.max():.3e} "
+              f"max_err/tol={(err / tol).max():.3f} nonzero={np.count_nonzero(ref)}", flush=True)
+        assert not bad.any(), (label, np.argwhere(bad)[:10])
     assert np.count_nonzero(ref) > 1000
     return got, ref
 
