@@ -422,7 +422,26 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         int j0 = min(max(fys, s.jlo), s.jhi);
         float rs2 = rho2_at(Xp, w, s.ts);
         int top = g.top;
+        Fire f;
+        bool fired = false;
         if (!miss) {
+            // The texel of the start point fires on its entry alone (its stored distance is
+            // below rho there): it is the piece's first fire.  The march would reach it by
+            // descending straight down from any level (every texel above it holds a minimum
+            // no larger, tested against a limit no smaller) and the whole-piece test would
+            // keep the piece, so both are skipped with the same result.  On the 1080p room
+            // most UNKNOWN results are of this kind: the ray enters the cell already behind
+            // the surface the probe sees.
+            const uint32_t k0 = ((uint32_t)j0 << g.logN) + (uint32_t)i0;
+            if (below(pyr_at(bp, base + k0), rs2)) {
+                f.i = i0;
+                f.j = j0;
+                f.tin = s.ts;
+                f.rin2 = rs2;
+                fired = true;
+            }
+        }
+        if (!miss & !fired) {
             // O(1) MISS test of the whole piece: its projection is a straight segment, so the
             // texels it crosses lie in the box spanned by its end points.  The box is widened
             // by N 2^-16 texels (2^-16 of the coordinate range, hundreds of ulps of the FP32
@@ -454,9 +473,7 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
             // on the 1080p room than starting at lv.
             top = min(top, max(lv - 1, 0));
         }
-        Fire f;
-        bool fired = false;
-        if (!miss) {
+        if (!miss & !fired) {
             piece_motion(s);
             fired = march_piece(g, bp, base, Xp, w, s, i0, j0, rs2, top, f);
         }
