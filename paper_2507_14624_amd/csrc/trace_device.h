@@ -324,11 +324,6 @@ __device__ bool march_piece(const GridDev &g, const float *bp, uint32_t base, co
             l += up;
             t = texit;
             rc2 = re2;
-            off = baseK - (K >> l);
-            // a crossing changes only with its own index or the level
-            if (ax | up) tx = next_x(s, I, l);
-            if (ay | up) ty = next_y(s, J, l);
-            continue;
         }
         off = baseK - (K >> l);
         tx = next_x(s, I, l);
