@@ -110,6 +110,15 @@ typedef struct {
                                  fetch it (traceOneProbe, highResolutionTracing), instead of
                                  the bilinear sample at the hit direction; the adjoint then
                                  has one tap per HIT ray */
+#define PT_FLAG_START_TEXEL 16u    /* decide a ray piece whose first texel already fires on
+                                      entry by that one level-0 load, skipping the whole-piece
+                                      test and the march (results identical either way).  By
+                                      default on when the level-0 distance maps of the grid
+                                      (of each level of a hierarchy) take at most 128 MiB, so
+                                      they stay in the last-level cache and the extra load per
+                                      piece pays for itself; off above, where it is an HBM
+                                      access per piece.  This flag forces it on ... */
+#define PT_FLAG_NO_START_TEXEL 32u /* ... and this one off (it wins if both are set) */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 

@@ -23,6 +23,8 @@ PT_FLAG_PERSISTENT = 1
 PT_FLAG_GRAPH = 2
 PT_FLAG_NEAREST = 4
 PT_FLAG_WIDE = 8
+PT_FLAG_START_TEXEL = 16
+PT_FLAG_NO_START_TEXEL = 32
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",

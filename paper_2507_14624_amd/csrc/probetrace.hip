@@ -697,6 +697,11 @@ static pt_status make_griddev(const pt_grid *g, const pt_trace_opts *opts, GridD
     for (int a = 0; a < 3; ++a) d.cmax[a] = d.few ? 0 : g->desc.dims[a] - 2;
     if (d.few) d.max_probes = std::min(d.max_probes, g->P);
     d.nearest = (o.flags & PT_FLAG_NEAREST) ? 1 : 0;
+    // the start-texel test pays while the level-0 distance maps stay in the last-level cache
+    const int64_t level0_bytes = (int64_t)g->P * g->N * g->N * (int64_t)sizeof(float);
+    d.start_test = (o.flags & PT_FLAG_NO_START_TEXEL) ? 0
+                   : (o.flags & PT_FLAG_START_TEXEL)  ? 1
+                                                      : (level0_bytes <= ((int64_t)128 << 20) ? 1 : 0);
     return PT_OK;
 }
 

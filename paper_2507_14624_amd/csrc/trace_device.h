@@ -45,6 +45,7 @@ struct GridDev {
     float inf;       // +INFINITY, set by the host (see min_nn)
     int cmax[3];     // last cell index per axis: n - 2, or 0 with fewer than 8 probes
     int few;         // fewer than 8 probes: one cell over the whole ray, every probe in its cage
+    int start_test;  // decide pieces whose first texel fires on entry without the march
 };
 
 // Layout of a probe's pyramid block (2 N^2 floats): every level keeps the row stride N of
@@ -424,14 +425,15 @@ __device__ void trace_probe(const GridDev &g, int pi, int pj, int pk, const floa
         int top = g.top;
         Fire f;
         bool fired = false;
-        if (!miss) {
+        if (!miss & (g.start_test != 0)) {
             // The texel of the start point fires on its entry alone (its stored distance is
             // below rho there): it is the piece's first fire.  The march would reach it by
             // descending straight down from any level (every texel above it holds a minimum
             // no larger, tested against a limit no smaller) and the whole-piece test would
             // keep the piece, so both are skipped with the same result.  On the 1080p room
             // most UNKNOWN results are of this kind: the ray enters the cell already behind
-            // the surface the probe sees.
+            // the surface the probe sees.  (The load costs a memory access per piece, which
+            // pays only while the level-0 maps stay in the cache: the host chooses.)
             const uint32_t k0 = ((uint32_t)j0 << g.logN) + (uint32_t)i0;
             if (below(pyr_at(bp, base + k0), rs2)) {
                 f.i = i0;

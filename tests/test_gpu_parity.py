@@ -212,6 +212,28 @@ def _batch_views(k=6, shrink=8):
             for v in views]
 
 
+@pytest.mark.parametrize("name,kw", [("tiny", {}), ("single", dict(size=(240, 135))),
+                                     ("diff", dict(N=64, levels=4, n_views=2, size=(96, 80)))])
+def test_start_texel_test_does_not_change_results(name, kw):
+    # deciding pieces whose first texel fires on entry without the march is exact: forced on
+    # and forced off give the same bits, per view and persistent
+    pt = _pt()
+    scene, probes, views, grid, rad = _grid(name, **kw)
+    for flags in (0, pt.PT_FLAG_PERSISTENT):
+        on = _gpu_numpy(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags | pt.PT_FLAG_START_TEXEL)))
+        off = _gpu_numpy(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags | pt.PT_FLAG_NO_START_TEXEL)))
+        both = _gpu_numpy(pt.probe_trace(grid, rad, views, pt.trace_opts(
+            flags=flags | pt.PT_FLAG_START_TEXEL | pt.PT_FLAG_NO_START_TEXEL)))
+        for k in on:
+            assert np.array_equal(on[k], off[k]), (flags, k)
+            assert np.array_equal(both[k], off[k]), (flags, k)
+    og = _oracle_grid(probes)
+    v = views[0]
+    n = v.width * v.height
+    assert_parity(compare({k: x[:n] for k, x in on.items()}, oracle.trace_view(og, v.as_tuple())),
+                  f"{name} start-texel test on")
+
+
 def test_multiview_plain_persistent_graph_identical():
     pt = _pt()
     scene, probes, views1, grid, rad = _grid("single", size=(240, 135))
