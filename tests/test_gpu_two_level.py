@@ -122,24 +122,26 @@ def test_two_level_backward_matches_oracle_vjp():
     gg = torch.zeros((tl.n_probes, tl.fine.N, tl.fine.N, 3), device="cuda")
     pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gg)
     got = gg.cpu().numpy().astype(np.float64)
-    # the persistent adjoint over both views gives the same sums up to atomic order
+    # the persistent adjoint over both views, and the adjoint from the forward's stored hits
+    # (coarse probes included): the same sums up to the order of the FP32 atomics, so each
+    # is held to the oracle with the same per-texel bound
     gp = torch.zeros_like(gg)
     pt.probe_trace_backward(grid, views, torch.from_numpy(g).cuda(), gp, pt.trace_opts(flags=pt.PT_FLAG_PERSISTENT))
-    torch.testing.assert_close(gp, gg, rtol=1e-5, atol=1e-6)
-    # and so does the adjoint from the forward's stored hits (coarse probes included)
     r2 = pt.probe_trace(grid, rad, views)
     gh = torch.zeros_like(gg)
     pt.probe_trace_backward_hits(grid, views, r2["hit"], r2["t"], torch.from_numpy(g).cuda(), gh)
-    torch.testing.assert_close(gh, gg, rtol=1e-5, atol=1e-6)
     ref = oracle.vjp((og, cg), orc, g.astype(np.float64))
     wabs = oracle.vjp((og, cg), orc, np.abs(g).astype(np.float64))
     unit = dict(orc)
     unit["wts"] = (orc["wts"] != 0).astype(np.float64)
     gabs = oracle.vjp((og, cg), unit, np.abs(g).astype(np.float64))
     tol = 1e-5 * wabs + 1e-3 * gabs + 1e-8
-    err = np.abs(got - ref)
-    print(f"[grad] city two-level max err/tol {(err / tol).max():.3f} nonzero {np.count_nonzero(ref)}", flush=True)
-    assert not (err > tol).any()
+    for label, x in (("per view", got), ("persistent", gp.cpu().numpy().astype(np.float64)),
+                     ("stored hits", gh.cpu().numpy().astype(np.float64))):
+        err = np.abs(x - ref)
+        print(f"[grad] city two-level {label} max err/tol {(err / tol).max():.3f} nonzero {np.count_nonzero(ref)}",
+              flush=True)
+        assert not (err > tol).any(), label
     assert np.count_nonzero(ref[tl.fine.n_probes:]) > 100  # coarse texels receive gradient
 
 
