@@ -141,12 +141,12 @@ def differentiable(pt, synth, torch, np, steps=5):
     rays = pt.n_rays(views)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed_fit(keep_hits):
-        fit = RadianceFit(grid, views, target, keep_hits=keep_hits)
+    def timed_fit(keep_hits, optimizer="fused"):
+        fit = RadianceFit(grid, views, target, keep_hits=keep_hits, optimizer=optimizer)
         for _ in range(3):  # warm-up on a throw-away fit
             fit.step()
         del fit
-        fit = RadianceFit(grid, views, target, keep_hits=keep_hits)  # timed from the initial radiance
+        fit = RadianceFit(grid, views, target, keep_hits=keep_hits, optimizer=optimizer)  # from the start
         losses = [fit.step().item()]
         torch.cuda.synchronize()
         e0.record()
@@ -155,9 +155,11 @@ def differentiable(pt, synth, torch, np, steps=5):
         torch.cuda.synchronize()
         return fit, e0.elapsed_time(e1) / steps, losses + [x.item() for x in out]
 
-    # the default adjoint from the forward's stored hits (no second trace), then the
-    # recomputing adjoint
+    # the default: adjoint from the forward's stored hits (no second trace) and the fused
+    # Adam step writing the FP16 storage; then torch's Adam; then the recomputing adjoint
     fit, ms_sh, losses_sh = timed_fit(True)
+    del fit
+    fit, ms_ta, losses_ta = timed_fit(True, "torch")
     del fit
     fit, ms, losses = timed_fit(False)
     # the trace kernels alone in one step: forward and backward
@@ -201,6 +203,9 @@ def differentiable(pt, synth, torch, np, steps=5):
             "adam_step_mrays_s": round(rays / (ms_sh * 1e-3) / 1e6, 2),
             "fwd_bwd_kernels_ms": round(ms_fh, 3), "fwd_bwd_mrays_s": round(rays / (ms_fh * 1e-3) / 1e6, 2),
             "adjoint": "from the forward's hit and t outputs (8 B/ray kept), no second trace",
+            "optimizer": "pt_adam_step: Adam on the FP32 master writing the FP16 storage in one pass",
+            "torch_adam": {"adam_step_ms": round(ms_ta, 3), "loss": [round(x, 6) for x in losses_ta],
+                           "optimizer": "torch.optim.Adam (fused) + an FP16 rounding pass per forward"},
             "recompute": {"adam_step_ms": round(ms, 3), "adam_step_mrays_s": round(rays / (ms * 1e-3) / 1e6, 2),
                           "fwd_bwd_kernels_ms": round(ms_fb, 3),
                           "fwd_bwd_mrays_s": round(rays / (ms_fb * 1e-3) / 1e6, 2),

@@ -268,6 +268,26 @@ pt_status probe_grid_set_distance(pt_grid *grid, const float *distance_dev, void
 pt_status probe_autotune(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
                          int32_t n_views, float *rgb_dev, pt_trace_opts *opts, void *stream);
 
+/* One Adam step over n FP32 parameters (Kingma and Ba's update as torch.optim.Adam makes
+ * it without amsgrad: with g = grad + weight_decay * param, m = beta1 m + (1 - beta1) g,
+ * v = beta2 v + (1 - beta2) g^2, param -= lr / (1 - beta1^step) * m /
+ * (sqrt(v) / sqrt(1 - beta2^step) + eps)), writing each updated parameter rounded to FP16
+ * (to nearest even) into half_out in the same pass: for fitting the radiance, the FP32
+ * master and the FP16 storage the trace reads, without a separate rounding pass.
+ *   param_dev, exp_avg_dev, exp_avg_sq_dev  [n] FP32, updated in place
+ *   grad_dev                                [n] FP32, read
+ *   half_out_dev                            [n] FP16 bits, written (NULL: not written)
+ *   step                                    1-based count of this step (bias correction)
+ * The scalars are doubles: the kernel's constants (1 - beta, the bias corrections, the step
+ * size) are formed in double and rounded once to FP32, so 1 - 0.999 is 0.001 and not the
+ * complement of 0.999 rounded to FP32.  Buffers must not overlap.  One streaming launch on
+ * `stream`.  Errors: INVALID_ARGUMENT
+ * (NULL buffers, n < 0, step < 1, lr or eps not finite and >= 0, betas outside [0, 1)),
+ * HIP. */
+pt_status pt_adam_step(float *param_dev, const float *grad_dev, float *exp_avg_dev, float *exp_avg_sq_dev,
+                       uint16_t *half_out_dev, int64_t n, int32_t step, double lr, double beta1, double beta2,
+                       double eps, double weight_decay, void *stream);
+
 const char *pt_last_error(void);
 
 #ifdef __cplusplus

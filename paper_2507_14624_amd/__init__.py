@@ -29,7 +29,7 @@ PT_FLAG_NO_START_TEXEL = 32
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",
             "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_hits",
-            "probe_trace_backward_distance", "probe_autotune", "pt_last_error")
+            "probe_trace_backward_distance", "probe_autotune", "pt_adam_step", "pt_last_error")
 
 
 class PtGridDesc(ctypes.Structure):
@@ -84,10 +84,12 @@ def load_library(path: str = LIB_PATH):
     lib.probe_grid_set_distance.argtypes = [vp, vp, vp]
     lib.probe_trace_backward_hits.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp,
                                               ctypes.POINTER(PtTraceOpts), vp]
+    f64 = ctypes.c_double
+    lib.pt_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, i32, f64, f64, f64, f64, f64, vp]
     for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
                  "probe_trace", "probe_trace_rays", "probe_grid_set_distance",
                  "probe_trace_backward", "probe_trace_backward_hits", "probe_trace_backward_distance",
-                 "probe_autotune"):
+                 "probe_autotune", "pt_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
     lib.pt_last_error.restype = ctypes.c_char_p
@@ -389,17 +391,40 @@ def probe_autotune(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | No
     return opts
 
 
+def adam_step(param, grad, exp_avg, exp_avg_sq, half_out, step: int, lr: float, betas=(0.9, 0.999),
+              eps: float = 1e-8, weight_decay: float = 0.0, stream=None):
+    """pt_adam_step: one Adam step on FP32 `param` in place (with its moments), writing
+    param rounded to FP16 into `half_out` (or nothing if None)."""
+    lib = load_library()
+    param = _dev_tensor(param, torch.float32, "param")
+    n = param.numel()
+    grad = _dev_tensor(grad, torch.float32, "grad")
+    exp_avg = _dev_tensor(exp_avg, torch.float32, "exp_avg")
+    exp_avg_sq = _dev_tensor(exp_avg_sq, torch.float32, "exp_avg_sq")
+    for t, what in ((grad, "grad"), (exp_avg, "exp_avg"), (exp_avg_sq, "exp_avg_sq")):
+        _need(t, n, what)
+    if half_out is not None:
+        half_out = _dev_tensor(half_out, torch.float16, "half_out")
+        _need(half_out, n, "half_out")
+    _check(lib.pt_adam_step(_ptr(param), _ptr(grad), _ptr(exp_avg), _ptr(exp_avg_sq),
+                            _ptr(half_out) if half_out is not None else None, int(n), int(step), float(lr),
+                            float(betas[0]), float(betas[1]), float(eps), float(weight_decay), _stream(stream)))
+    return param
+
+
 class ProbeTraceFn(torch.autograd.Function):
     """rgb = trace(radiance) with the hit test held fixed.
 
-    forward: the FP32 master radiance is rounded to the FP16 storage the trace reads;
+    forward: the FP32 master radiance is rounded to the FP16 storage the trace reads (or
+    `storage`, the caller's FP16 rounding of master, is read as it is);
     backward: probe_trace_backward into a zeroed FP32 buffer, passed straight through the
     FP16 rounding to the master.  keep_hits=True keeps the forward's hit and t outputs (8
     bytes per ray) and runs probe_trace_backward_hits instead of recomputing the trace."""
 
     @staticmethod
-    def forward(ctx, master, grid, views, opts=None, keep_hits=False):
-        storage = master.detach().to(torch.float16).contiguous()
+    def forward(ctx, master, grid, views, opts=None, keep_hits=False, storage=None):
+        if storage is None:
+            storage = master.detach().to(torch.float16).contiguous()
         va = views if isinstance(views, ctypes.Array) else make_views(views)
         res = probe_trace(grid, storage, va, opts, want_t=keep_hits, want_status=False, want_hit=keep_hits)
         ctx.grid, ctx.views, ctx.opts = grid, va, opts
@@ -415,7 +440,7 @@ class ProbeTraceFn(torch.autograd.Function):
                                       ctx.opts)
         else:
             probe_trace_backward(ctx.grid, ctx.views, grad_rgb.contiguous().float(), g, ctx.opts)
-        return g, None, None, None, None
+        return g, None, None, None, None, None
 
 
 class ProbeGeometryFn(torch.autograd.Function):

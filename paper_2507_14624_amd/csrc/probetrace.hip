@@ -2,6 +2,7 @@
 // Kernels: pyramid build, per-view trace, arbitrary-ray trace, persistent multi-view
 // trace over a device tile queue (optionally captured in a hipGraph), the radiance
 // adjoint, and probe baking from a point cloud.  The contract is in include/probetrace.h.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1114,6 +1115,110 @@ __global__ void k_pack_distance(const float *__restrict__ dist, float *__restric
     if (g >= total) return;
     int64_t NN = (int64_t)N * N;
     pyr[(g / NN) * stride + g % NN] = dist[g];
+}
+
+// ------------------------------------------------------------------------------------
+// Adam step over an FP32 master that also writes its FP16 rounding (the trace's storage)
+// ------------------------------------------------------------------------------------
+struct AdamConst {
+    float step_size;  // lr / (1 - beta1^step)
+    float sqrt_bc2;   // sqrt(1 - beta2^step)
+    float beta2, omb1, omb2, eps, wd;
+};
+
+// m moves toward g by 1 - beta1; v = beta2 v + (1 - beta2) g^2; the step divides m by
+// sqrt(v) / sqrt(bc2) + eps: the operations of the textbook update, one rounding each
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, const AdamConst &c) {
+    g = g + c.wd * p;
+    m = m + c.omb1 * (g - m);
+    v = c.beta2 * v + c.omb2 * g * g;
+    const float denom = sqrtf(v) / c.sqrt_bc2 + c.eps;
+    p = p - c.step_size * (m / denom);
+}
+
+// Vec: four elements per lane with 16-byte loads (all buffers 16-byte aligned, the FP16
+// output 8-byte aligned); the last n % 4 elements, or every element of misaligned
+// buffers, one per lane.  A streaming pass: 30 bytes per element (read p, g, m, v; write
+// p, m, v, h).
+template <bool Vec>
+__global__ void __launch_bounds__(256) k_adam_fp16(float *__restrict__ p, const float *__restrict__ g,
+                                                   float *__restrict__ m, float *__restrict__ v,
+                                                   __half *__restrict__ h, int64_t begin, int64_t n,
+                                                   AdamConst c) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (Vec) {
+        const int64_t n4 = n >> 2;
+        for (; i < n4; i += stride) {
+            float4 P = reinterpret_cast<float4 *>(p)[i];
+            const float4 G = reinterpret_cast<const float4 *>(g)[i];
+            float4 M = reinterpret_cast<float4 *>(m)[i];
+            float4 V = reinterpret_cast<float4 *>(v)[i];
+            adam_one(P.x, G.x, M.x, V.x, c);
+            adam_one(P.y, G.y, M.y, V.y, c);
+            adam_one(P.z, G.z, M.z, V.z, c);
+            adam_one(P.w, G.w, M.w, V.w, c);
+            reinterpret_cast<float4 *>(p)[i] = P;
+            reinterpret_cast<float4 *>(m)[i] = M;
+            reinterpret_cast<float4 *>(v)[i] = V;
+            if (h) {
+                __half2 lo = __halves2half2(__float2half_rn(P.x), __float2half_rn(P.y));
+                __half2 hi = __halves2half2(__float2half_rn(P.z), __float2half_rn(P.w));
+                reinterpret_cast<__half2 *>(h)[2 * i] = lo;
+                reinterpret_cast<__half2 *>(h)[2 * i + 1] = hi;
+            }
+        }
+    } else {
+        for (i += begin; i < n; i += stride) {
+            float P = p[i], M = m[i], V = v[i];
+            adam_one(P, g[i], M, V, c);
+            p[i] = P;
+            m[i] = M;
+            v[i] = V;
+            if (h) h[i] = __float2half_rn(P);
+        }
+    }
+}
+
+extern "C" pt_status pt_adam_step(float *param_dev, const float *grad_dev, float *exp_avg_dev,
+                                  float *exp_avg_sq_dev, uint16_t *half_out_dev, int64_t n, int32_t step, double lr,
+                                  double beta1, double beta2, double eps, double weight_decay, void *stream) {
+    if (!param_dev || !grad_dev || !exp_avg_dev || !exp_avg_sq_dev)
+        return fail(PT_ERR_INVALID_ARGUMENT, "pt_adam_step: NULL argument");
+    if (n < 0 || step < 1) return fail(PT_ERR_INVALID_ARGUMENT, "pt_adam_step: n < 0 or step < 1");
+    if (!(lr >= 0.0) || !std::isfinite(lr) || !(eps >= 0.0) || !std::isfinite(eps) || !(beta1 >= 0.0) ||
+        !(beta1 < 1.0) || !(beta2 >= 0.0) || !(beta2 < 1.0) || !std::isfinite(weight_decay))
+        return fail(PT_ERR_INVALID_ARGUMENT, "pt_adam_step: lr, eps, betas or weight_decay out of range");
+    if (n == 0) return PT_OK;
+    AdamConst c;
+    c.step_size = (float)(lr / (1.0 - std::pow(beta1, (double)step)));
+    c.sqrt_bc2 = (float)std::sqrt(1.0 - std::pow(beta2, (double)step));
+    c.beta2 = (float)beta2;
+    c.omb1 = (float)(1.0 - beta1);
+    c.omb2 = (float)(1.0 - beta2);
+    c.eps = (float)eps;
+    c.wd = (float)weight_decay;
+    hipStream_t s = (hipStream_t)stream;
+    __half *h = reinterpret_cast<__half *>(half_out_dev);
+    auto aligned = [](const void *q, uintptr_t a) { return q == nullptr || ((uintptr_t)q % a) == 0; };
+    const bool vec = aligned(param_dev, 16) && aligned(grad_dev, 16) && aligned(exp_avg_dev, 16) &&
+                     aligned(exp_avg_sq_dev, 16) && aligned(half_out_dev, 8);
+    // a few waves per SIMD of a grid-stride loop: 256 CUs x 8 workgroups
+    const int64_t lanes = vec ? (n >> 2) : n;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(lanes, 256), 2048));
+    if (vec) {
+        hipLaunchKernelGGL(k_adam_fp16<true>, dim3(nb), dim3(256), 0, s, param_dev, grad_dev, exp_avg_dev,
+                           exp_avg_sq_dev, h, (int64_t)0, n, c);
+        const int64_t tail = n & ~(int64_t)3;
+        if (tail < n)
+            hipLaunchKernelGGL(k_adam_fp16<false>, dim3(1), dim3(256), 0, s, param_dev, grad_dev, exp_avg_dev,
+                               exp_avg_sq_dev, h, tail, n, c);
+    } else {
+        hipLaunchKernelGGL(k_adam_fp16<false>, dim3(nb), dim3(256), 0, s, param_dev, grad_dev, exp_avg_dev,
+                           exp_avg_sq_dev, h, (int64_t)0, n, c);
+    }
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
 }
 
 extern "C" pt_status probe_grid_set_distance(pt_grid *g, const float *distance_dev, void *stream) {

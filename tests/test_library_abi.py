@@ -65,4 +65,11 @@ def test_host_side_argument_errors():
     o = pt.PtTraceOpts()
     lib.pt_trace_opts_default(ctypes.byref(o))
     assert o.max_probes_per_cell == 8 and o.tile_w * o.tile_h == 64 and o.start_level == -1
+    # the optimizer step checks its arguments before any launch
+    assert lib.pt_adam_step(None, None, None, None, None, 8, 1, 1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 1
+    assert b"NULL" in lib.pt_last_error()
+    for n, step, lr, b1, b2, eps in ((-1, 1, 1e-3, 0.9, 0.999, 1e-8), (8, 0, 1e-3, 0.9, 0.999, 1e-8),
+                                     (8, 1, -1.0, 0.9, 0.999, 1e-8), (8, 1, 1e-3, 1.0, 0.999, 1e-8),
+                                     (8, 1, 1e-3, 0.9, 1.5, 1e-8), (8, 1, 1e-3, 0.9, 0.999, float("inf"))):
+        assert lib.pt_adam_step(dummy, dummy, dummy, dummy, None, n, step, lr, b1, b2, eps, 0.0, None) == 1
     lib.probe_grid_destroy(None)  # ignored
