@@ -79,11 +79,13 @@ typedef struct {
 /* Pinhole camera: pixel (x, y), row 0 at the top, has direction
  *   normalize(fwd + ((2(x+1/2)/W - 1) (W/H) tan_half_fov_y) right
  *                 + ((1 - 2(y+1/2)/H) tan_half_fov_y) up)
- * from pos.  Rays of one view are stored row-major (y*W + x). */
+ * from pos.  Rays of one view are stored row-major (y*W + x).  Calls taking views return
+ * INVALID_ARGUMENT for a non-finite pos, right, up or fwd component, a tan_half_fov_y not
+ * finite and > 0, or a side outside [1, 65536]. */
 typedef struct {
     float pos[3], right[3], up[3], fwd[3];
     float tan_half_fov_y;
-    int32_t width, height; /* >= 1 */
+    int32_t width, height; /* 1 .. 65536 */
 } pt_view;
 
 /* Algorithm constants and tuning knobs.  pt_trace_opts_default() fills the defaults. */

@@ -783,6 +783,10 @@ static pt_status check_views(const pt_view *views, int n_views, int tw, int th, 
             return fail(PT_ERR_INVALID_ARGUMENT, "view size out of range");
         if (!(v.tan_half_fov_y > 0.0f) || !std::isfinite(v.tan_half_fov_y))
             return fail(PT_ERR_INVALID_ARGUMENT, "tan_half_fov_y must be finite and > 0");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(v.pos[a]) || !std::isfinite(v.right[a]) || !std::isfinite(v.up[a]) ||
+                !std::isfinite(v.fwd[a]))
+                return fail(PT_ERR_INVALID_ARGUMENT, "view position and axes must be finite");
         ViewDev &d = vd[i];
         for (int a = 0; a < 3; ++a) {
             d.pos[a] = v.pos[a];

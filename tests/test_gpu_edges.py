@@ -93,6 +93,20 @@ def test_largest_view_side_and_the_first_refused():
             pt.probe_trace(grid, rad, [_resized(v0, *bad)])
     with pytest.raises(pt.ProbeTraceError):
         pt.probe_trace(grid, rad, [synth.View(v0.pos, v0.right, v0.up, v0.fwd, 0.0, 4, 4)])
+    # non-finite camera parameters are refused before any launch, for every entry point
+    # that takes views
+    for field in ("pos", "right", "up", "fwd"):
+        for bad in (np.nan, np.inf):
+            kw = dict(pos=v0.pos, right=v0.right, up=v0.up, fwd=v0.fwd)
+            vec = np.array(kw[field], np.float64)
+            vec[1] = bad
+            kw[field] = vec
+            v = synth.View(kw["pos"], kw["right"], kw["up"], kw["fwd"], v0.tan_half_fov_y, 4, 4)
+            with pytest.raises(pt.ProbeTraceError, match="finite"):
+                pt.probe_trace(grid, rad, [v])
+            with pytest.raises(pt.ProbeTraceError, match="finite"):
+                pt.probe_trace_backward(grid, [v], torch.zeros((16, 3), device="cuda"),
+                                        torch.zeros((probes.n_probes, probes.N, probes.N, 3), device="cuda"))
 
 
 def test_empty_ray_batch():
