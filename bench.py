@@ -351,8 +351,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(rays shard by view with replicated probes; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (rays would shard by "
+              "view, with the probe set replicated on every GPU).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
