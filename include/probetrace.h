@@ -52,7 +52,7 @@ typedef enum {
     PT_ERR_INVALID_ARGUMENT = 1, /* a host-side check failed; nothing was enqueued */
     PT_ERR_OUT_OF_MEMORY = 2,    /* a library allocation failed */
     PT_ERR_HIP = 3,              /* a HIP call failed (message names it) */
-    PT_ERR_UNSUPPORTED = 4       /* a valid request this build does not support */
+    PT_ERR_UNSUPPORTED = 4       /* a valid request the library does not support */
 } pt_status;
 
 /* per-ray classification (Ray Tracing Using One Probe): the final status of a camera ray
