@@ -53,6 +53,20 @@ def measured_traffic():
     return float(m.group(1))
 
 
+def measured_valu():
+    """(VALU instructions per wavefront, wavefronts per launch) of the forward from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    v = re.search(r"\| VALU instructions / wavefront \| ([0-9.]+) \|", text)
+    w = re.search(r"\| wavefronts \| ([0-9]+) \|", text)
+    s = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    if not v or not w or not s or s.group(1) != kernel_source_hash():
+        return None
+    return float(v.group(1)), int(w.group(1))
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -417,6 +431,15 @@ def main():
                              "algorithmic_bytes_per_launch": ab["total_bytes"],
                              "bytes_per_ray": round(ab["bytes_per_ray"], 2)}},
     }
+    valu = measured_valu()
+    tiles = -(-view.width // opts.tile_w) * -(-view.height // opts.tile_h)  # one wavefront per tile
+    if valu is not None and valu[1] == tiles:  # the profiled launch had this shape
+        # issue time of the VALU instructions the counters saw (4 cycles per wave64
+        # instruction on 1,024 SIMDs at 2.4 GHz) against this run's launch duration
+        issue_ms = valu[0] * valu[1] * 4 / (1024 * 2.4e9) * 1e3
+        result["roofline"]["valu_issue"] = {"instructions_per_launch": int(valu[0] * valu[1]),
+                                            "issue_ms": round(issue_ms, 4), "frac": round(issue_ms / ms, 4),
+                                            "source": "rocprofv3 SQ_INSTS_VALU (profiles/)"}
     if not args.no_extras:
         gsz = (probes.n_probes, probes.N, probes.N, 3)
         grad = torch.zeros(gsz, device="cuda")
