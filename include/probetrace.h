@@ -223,7 +223,9 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
  * ([rays] FP32) exactly as probe_trace wrote them for these views and this grid.  The
  * sample direction of each HIT is rebuilt from (probe, t) with the forward's operations, so
  * the result equals probe_trace_backward's up to the order of the FP32 atomics; the march
- * is not repeated (8 bytes per ray of storage against a second trace).  One launch over the
+ * is not repeated (8 bytes per ray of storage against a second trace).  Entries whose probe
+ * is outside [0, P) or texel outside [0, N^2) add nothing (no write outside grad_radiance
+ * for any hit_dev contents).  One launch over the
  * pixel tiles of all views, one tile of opts' tile shape per wavefront.  Errors:
  * INVALID_ARGUMENT (NULL buffers, bad views or tile shape), HIP. */
 pt_status probe_trace_backward_hits(const pt_grid *grid, const pt_view *views_host, int32_t n_views,

@@ -600,7 +600,14 @@ __global__ void __launch_bounds__(256) k_backward_hits(GridDev g, Level2 L2, con
     int64_t key[4] = {-1, -1, -1, -1};
     float val[4][3] = {};
     const int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
-    const int p = (x < v.W && y < v.H) ? hit[2 * ray] : -1;
+    int p = -1, texel = -1;
+    if (x < v.W && y < v.H) {
+        p = hit[2 * ray];
+        texel = hit[2 * ray + 1];
+    }
+    // entries that name no probe or texel of this grid (not a forward's output) add nothing
+    const int p_total = g.P + (T == kTwoLevel ? L2.c.P : 0);
+    if (p >= p_total || (unsigned)texel >= (unsigned)(g.N * g.N)) p = -1;
     if (p >= 0) {
         float w[3];
         camera_ray(v, x, y, w);
@@ -614,7 +621,7 @@ __global__ void __launch_bounds__(256) k_backward_hits(GridDev g, Level2 L2, con
         RayResult r;
         r.status = ST_HIT;
         r.probe = p;
-        r.texel = hit[2 * ray + 1];
+        r.texel = texel;
         r.t = tt[ray];
         r.eye = __fmaf_rn(Xp[2], Xp[2], __fmaf_rn(Xp[1], Xp[1], Xp[0] * Xp[0])) <= G.eye_eps2;
 #pragma unroll

@@ -206,3 +206,28 @@ def test_autograd_with_stored_hits():
         ((rgb - target) ** 2).mean().backward()
         grads.append(master.grad.clone())
     torch.testing.assert_close(grads[1], grads[0], rtol=1e-5, atol=1e-7)
+
+
+def test_stored_hits_outside_the_grid_add_nothing():
+    # hit entries that are no forward output (probe beyond the grid, texel beyond the map)
+    # contribute nothing and write nowhere: the same gradient as with those rays marked MISS
+    pt, scene, probes, views, grid, rad = _setup("tiny")
+    res = pt.probe_trace(grid, rad, views[:1])
+    rays = res["rgb"].shape[0]
+    gen = torch.Generator(device="cpu").manual_seed(8)
+    gr = torch.randn((rays, 3), generator=gen).cuda()
+    hit = res["hit"].clone()
+    bad = torch.arange(0, rays, 97, device="cuda")
+    N2 = probes.N * probes.N
+    vals = torch.tensor([[probes.n_probes, 0], [probes.n_probes + 5, 3], [2 ** 30, 7], [0, N2], [1, N2 + 11],
+                         [0, -5]], dtype=torch.int32, device="cuda")
+    hit[bad] = vals[torch.arange(len(bad), device="cuda") % len(vals)]
+    miss = res["hit"].clone()
+    miss[bad] = -1
+    shape = (probes.n_probes, probes.N, probes.N, 3)
+    a = torch.zeros(shape, device="cuda")
+    b = torch.zeros(shape, device="cuda")
+    pt.probe_trace_backward_hits(grid, views[:1], hit, res["t"], gr, a)
+    pt.probe_trace_backward_hits(grid, views[:1], miss, res["t"], gr, b)
+    torch.testing.assert_close(a, b, rtol=1e-5, atol=1e-5)
+    assert torch.count_nonzero(b).item() > 1000
