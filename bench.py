@@ -216,7 +216,7 @@ def differentiable(pt, synth, torch, np, steps=5):
             "rays_per_step": rays, "adam_step_ms": round(ms_sh, 3),
             "adam_step_mrays_s": round(rays / (ms_sh * 1e-3) / 1e6, 2),
             "fwd_bwd_kernels_ms": round(ms_fh, 3), "fwd_bwd_mrays_s": round(rays / (ms_fh * 1e-3) / 1e6, 2),
-            "adjoint": "from the forward's hit and t outputs (8 B/ray kept), no second trace",
+            "adjoint": "from the forward's hit and t outputs (12 B/ray kept: probe and texel as int32, t as FP32), no second trace",
             "optimizer": "pt_adam_step: Adam on the FP32 master writing the FP16 storage in one pass",
             "torch_adam": {"adam_step_ms": round(ms_ta, 3), "loss": [round(x, 6) for x in losses_ta],
                            "optimizer": "torch.optim.Adam (fused) + an FP16 rounding pass per forward"},
@@ -465,7 +465,7 @@ def main():
         ms_fh, _ = time_steps(fwd_bwd_hits, max(3, args.steps // 2), 1, torch)
         result["fwd_bwd_stored_hits"] = {"value": round(rays / (ms_fh * 1e-3) / 1e6, 3), "unit": "Mrays/s",
                                          "ms_per_step": round(ms_fh, 4),
-                                         "adjoint": "from the forward's hit and t outputs (8 B/ray kept)"}
+                                         "adjoint": "from the forward's hit and t outputs (12 B/ray kept: probe and texel as int32, t as FP32)"}
         print("[bench] batched workload", file=sys.stderr, flush=True)
         _, _, bviews = synth.workload("batched")
         bva = pt.make_views(bviews)

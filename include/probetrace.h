@@ -61,7 +61,8 @@ typedef enum { PT_MISS = 0, PT_HIT = 1, PT_UNKNOWN = 2 } pt_ray_status;
 
 typedef struct pt_grid pt_grid; /* opaque: the probe geometry resident on one device */
 
-/* Uniform probe grid (Figure 3(a): probes at the vertices of a uniform 3D grid).  A layout
+/* Uniform probe grid (Ray Trace Using Multiple Probes, Figure 3(a): one probe on every grid
+ * point of a regular 3D lattice).  A layout
  * of fewer than 8 probes (Ray Trace Using Multiple Probes, less than 8 probes) has no grid
  * iterator: every ray tries all its probes, closest to the eye first (ties by probe index),
  * over its whole length. */
@@ -223,7 +224,8 @@ pt_status probe_trace_backward(const pt_grid *grid, const pt_view *views_host, i
  * ([rays] FP32) exactly as probe_trace wrote them for these views and this grid.  The
  * sample direction of each HIT is rebuilt from (probe, t) with the forward's operations, so
  * the result equals probe_trace_backward's up to the order of the FP32 atomics; the march
- * is not repeated (8 bytes per ray of storage against a second trace).  Entries whose probe
+ * is not repeated (12 bytes per ray of storage, probe and texel as int32 plus t as FP32,
+ * against a second trace).  Entries whose probe
  * is outside [0, P) or texel outside [0, N^2) add nothing (no write outside grad_radiance
  * for any hit_dev contents).  One launch over the
  * pixel tiles of all views, one tile of opts' tile shape per wavefront.  Errors:

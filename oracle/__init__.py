@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("status", "t", "rgb", "probe", "texel", "margin", "tests", "normals", "flat_tests", "rank",
-                 "taps", "wts", "score", "work", "dtdr", "drgbdt", "kink")]
+                 "taps", "wts", "score", "work", "dtdr", "drgbdt", "kink", "tcond")]
 
 
 def build_native(force: bool = True) -> str:
@@ -89,6 +89,11 @@ def _load():
         lib.oracle_texel_sequence.restype = ctypes.c_int
         lib.oracle_bilinear_taps.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p]
+        lib.oracle_cell_walk.argtypes = [ctypes.POINTER(_Grid), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_cell_walk.restype = ctypes.c_int
+        lib.oracle_cage_order.argtypes = [ctypes.POINTER(_Grid), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_cage_order.restype = ctypes.c_int
         lib.oracle_half_to_double.argtypes = [ctypes.c_uint16]
         lib.oracle_half_to_double.restype = ctypes.c_double
         _lib = lib
@@ -219,7 +224,7 @@ class _Level2(ctypes.Structure):
 
 def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) -> dict:
     """Trace rays; returns per-ray arrays (status, t, rgb, probe, texel, margin, tests,
-    normals, flat_tests, rank, taps, wts, score, work).  ``score`` is the smallest gap/error-scale
+    normals, flat_tests, rank, taps, wts, score, work, dtdr, drgbdt, kink, tcond).  ``score`` is the smallest gap/error-scale
     ratio over the ray's decisions; ``margin`` has a bit per decision kind with ratio <= delta;
     ``work`` counts probe traces, pieces marched and cells visited."""
     lib = _load()
@@ -242,7 +247,7 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) 
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),
                rank=np.empty(n, np.int32), taps=np.empty((n, 4), np.int32), wts=np.empty((n, 4), np.float64),
                score=np.empty(n, np.float64), work=np.empty((n, 3), np.int32), dtdr=np.empty(n, np.float64),
-               drgbdt=np.empty((n, 3), np.float64), kink=np.empty(n, np.int32))
+               drgbdt=np.empty((n, 3), np.float64), kink=np.empty(n, np.int32), tcond=np.empty(n, np.float64))
     out = _Out()
     for k, v in res.items():
         setattr(out, k, v.ctypes.data)
@@ -346,6 +351,32 @@ def texel_sequence(N: int, xp, w, ta: float, tb: float, cap: int = 100000):
                                   _ptr(piece))
     n = min(n, cap)
     return ij[:n].copy(), tio[:n].copy(), piece[:n].copy()
+
+
+def cell_walk(grid: Grid, X, w, cap: int = 4096):
+    """The grid iterator's walk of the ray (X, w) (Ray Trace Using Multiple Probes > Grid
+    Iterator): arrays (cells [n,3] int, intervals [n,2] = (ta, tb)) in ray order."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    cells = np.empty((cap, 3), np.int32)
+    tab = np.empty((cap, 2), np.float64)
+    g = grid._struct()
+    n = lib.oracle_cell_walk(ctypes.byref(g), _ptr(X), _ptr(w), cap, _ptr(cells), _ptr(tab))
+    n = min(n, cap)
+    return cells[:n].copy(), tab[:n].copy()
+
+
+def cage_order(grid: Grid, cell, X) -> np.ndarray:
+    """Probe indices of the cage of `cell` in the order the trace tries them for a ray
+    from X (Ray Trace Using Multiple Probes > Less Than 8 Probes)."""
+    lib = _load()
+    c = np.ascontiguousarray(cell, dtype=np.int32)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.empty(8, np.int32)
+    g = grid._struct()
+    n = lib.oracle_cage_order(ctypes.byref(g), _ptr(c), _ptr(X), _ptr(out))
+    return out[:n].copy()
 
 
 def bilinear_taps(u: float, v: float, N: int):

@@ -66,6 +66,12 @@ enum { ST_MISS = 0, ST_HIT = 1, ST_UNKNOWN = 2 };
 #define MG_THIT 256    /* hit distance ill-conditioned */
 #define MG_HIER 512    /* hierarchical schedule disagreed with the flat march */
 
+/* The hit distance counts as ill-conditioned (MG_THIT) where a computation in FP32 can miss
+ * it by the 1e-4 relative tolerance of the GPU acceptance: a few FP32 unit roundoffs times
+ * its first-order condition scale reach 1e-4 t. */
+#define THIT_ROUNDOFF (4.0 * 0x1p-24)
+#define THIT_TOL 1e-4
+
 typedef struct {
     int32_t dims[3];
     int32_t N, levels;
@@ -125,6 +131,8 @@ typedef struct {
     double *drgbdt;    /* [n][3] d rgb / d t_hit: the radiance sample moving with the hit point (nullable) */
     int32_t *kink;     /* [n] bit 0: the hit is within the margin of switching between the texel's
                           entry point and the root, where t(r) is continuous but dt/dr jumps (nullable) */
+    double *tcond;     /* [n] first-order condition scale of t_hit: a relative error u in the inputs and
+                          operations moves t by about u tcond (0 for the eye lookup and non-HIT rays; nullable) */
 } out_t;
 
 /* ------------------------------------------------------------------------------------
@@ -510,6 +518,7 @@ typedef struct {
                        entry hit, r / sqrt(r^2 - d_perp^2) for the root */
     int eye;        /* hit by the eye-aligned lookup (the sample direction is w itself) */
     int kink;       /* bit 0: rho_in within the margin of r (entry point vs root) */
+    double tcond;   /* condition scale of t (entry crossing, or the root) */
     int tests, normals, flat_tests, pieces;
 } presult_t;
 
@@ -627,8 +636,9 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
         if (ff.rin >= rk) {
             th = ff.tin;
             res->dtdr = 0.0; /* the entry point does not move with r */
+            res->tcond = ff.Ein;
             /* the entry crossing's condition scale decides how well t is known */
-            if (1e-2 * ff.Ein > fabs(th)) mc->bits |= MG_THIT;
+            if (THIT_ROUNDOFF * ff.Ein > THIT_TOL * fabs(th)) mc->bits |= MG_THIT;
         } else {
             double b = r.Xp[0] * w[0] + r.Xp[1] * w[1] + r.Xp[2] * w[2];
             double pv[3] = {r.Xp[0] - b * w[0], r.Xp[1] - b * w[1], r.Xp[2] - b * w[2]};
@@ -636,9 +646,13 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
             double disc = (rk - dp) * (rk + dp);
             if (disc < 0) disc = 0;
             double sq = sqrt(disc);
-            if (sq <= 1e-2 * rk) mc->bits |= MG_THIT;
             if (b <= 0) th = -b + sq;
             else th = (rk - dist) * (rk + dist) / (b + sq);
+            /* condition scale of the root: errors of size u (S + r) in r and in the distance
+             * of the ray from the probe move sq = sqrt(r^2 - d_perp^2) by u (S + r) r / sq, and
+             * b by u S */
+            res->tcond = sq > 0 ? (r.S + rk) * rk / sq + r.S : INFINITY;
+            if (THIT_ROUNDOFF * res->tcond > THIT_TOL * fabs(th)) mc->bits |= MG_THIT;
             /* t = -b + sqrt(r^2 - d_perp^2): dt/dr = r / sqrt(...) (infinite at tangency) */
             res->dtdr = sq > 0 ? rk / sq : INFINITY;
         }
@@ -696,6 +710,89 @@ static int cage_sort(const grid_t *g, const int cell[3], const double X[3], int 
     return n;
 }
 
+/* Grid iterator (Ray Trace Using Multiple Probes > Grid Iterator): the cells of the probe
+ * grid the ray crosses, in ray order, each with its parameter interval [ta, tb].  Cells are
+ * bounded by the interior probe planes only, so the outer cells extend without bound and
+ * every ray point has a cell; the walk starts at t = 0 and ends where the ray leaves the
+ * (slightly enlarged) scene box, t_far.  Near ties of the planes' crossings are margin
+ * decisions (mc nullable). */
+typedef struct {
+    const grid_t *g;
+    double X[3], w[3];
+    int cell[3];
+    double ta, Eta, tfar, Efar;
+    int done;
+} citer_t;
+
+static void citer_init(citer_t *it, const grid_t *g, const double X[3], const double w[3], mctx_t *mc) {
+    it->g = g;
+    memcpy(it->X, X, sizeof(double) * 3);
+    memcpy(it->w, w, sizeof(double) * 3);
+    /* parameter range: until the ray leaves the scene box (slightly enlarged) */
+    double tfar = INFINITY, Efar = 0;
+    for (int a = 0; a < 3; ++a) {
+        double t = INFINITY;
+        if (w[a] > 0) t = (g->smax[a] - X[a]) / w[a];
+        else if (w[a] < 0) t = (g->smin[a] - X[a]) / w[a];
+        if (t < tfar) {
+            tfar = t;
+            Efar = (fabs(g->smax[a]) + fabs(g->smin[a]) + fabs(X[a]) + fabs(t)) / fabs(w[a]);
+        }
+    }
+    it->tfar = tfar * (1.0 + 1e-4);
+    it->Efar = Efar;
+    for (int a = 0; a < 3; ++a) {
+        double q = (X[a] - g->origin[a]) / g->spacing[a];
+        it->cell[a] = clampi((int)floor(q), 0, cell_max(g, a));
+        double c = floor(q + 0.5);
+        if (mc && c >= 1 && c <= cell_max(g, a)) decide(mc, q - c, 4.0 * (fabs(X[a]) + fabs(g->origin[a])), MG_CELL);
+    }
+    it->ta = 0.0;
+    it->Eta = 0.0;
+    it->done = !(it->ta < it->tfar && it->tfar > 0);
+}
+
+/* The next cell and its interval; 0 once the ray has left the scene box. */
+static int citer_next(citer_t *it, mctx_t *mc, int cell[3], double *ta, double *Eta, double *tb, double *Etb) {
+    if (it->done) return 0;
+    const grid_t *g = it->g;
+    /* next interior grid plane along each axis */
+    double tn[3], En[3];
+    for (int a = 0; a < 3; ++a) {
+        tn[a] = INFINITY; En[a] = 0;
+        int pidx = -1;
+        if (it->w[a] > 0 && it->cell[a] + 1 <= cell_max(g, a)) pidx = it->cell[a] + 1;
+        else if (it->w[a] < 0 && it->cell[a] >= 1) pidx = it->cell[a];
+        if (pidx >= 0) {
+            double plane = g->origin[a] + pidx * g->spacing[a];
+            tn[a] = (plane - it->X[a]) / it->w[a];
+            En[a] = (fabs(plane) + fabs(it->X[a]) + fabs(tn[a])) / fabs(it->w[a]);
+        }
+    }
+    double b = it->tfar, Eb = it->Efar;
+    for (int a = 0; a < 3; ++a)
+        if (tn[a] < b) { b = tn[a]; Eb = En[a]; }
+    if (mc)
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(tn[a])) continue;
+            decide(mc, tn[a] - it->tfar, En[a] + it->Efar, MG_CELL);
+            for (int c = a + 1; c < 3; ++c)
+                if (isfinite(tn[c])) decide(mc, tn[a] - tn[c], En[a] + En[c], MG_CELL);
+        }
+    memcpy(cell, it->cell, sizeof(int) * 3);
+    *ta = it->ta; *Eta = it->Eta; *tb = b; *Etb = Eb;
+    /* advance: every axis whose plane is crossed at tb steps (a tie steps several) */
+    if (b >= it->tfar) {
+        it->done = 1;
+    } else {
+        for (int a = 0; a < 3; ++a)
+            if (tn[a] == b) it->cell[a] += it->w[a] > 0 ? 1 : -1;
+        it->ta = b;
+        it->Eta = Eb;
+    }
+    return 1;
+}
+
 static inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, const double X[3], const double win[3],
@@ -708,53 +805,15 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
     mc.score = INFINITY;
     mc.delta = o->delta;
     int tests = 0, normals = 0, flat_tests = 0, n_probe = 0, n_piece = 0, n_cell = 0;
-    /* parameter range: until the ray leaves the scene box (slightly enlarged) */
-    double tfar = INFINITY, Efar = 0;
-    for (int a = 0; a < 3; ++a) {
-        double t = INFINITY;
-        if (w[a] > 0) t = (g->smax[a] - X[a]) / w[a];
-        else if (w[a] < 0) t = (g->smin[a] - X[a]) / w[a];
-        if (t < tfar) {
-            tfar = t;
-            Efar = (fabs(g->smax[a]) + fabs(g->smin[a]) + fabs(X[a]) + fabs(t)) / fabs(w[a]);
-        }
-    }
-    tfar *= 1.0 + 1e-4;
     int any_unknown = 0;
-    int cell[3];
-    for (int a = 0; a < 3; ++a) {
-        double q = (X[a] - g->origin[a]) / g->spacing[a];
-        cell[a] = clampi((int)floor(q), 0, cell_max(g, a));
-        double c = floor(q + 0.5);
-        if (c >= 1 && c <= cell_max(g, a)) decide(&mc, q - c, 4.0 * (fabs(X[a]) + fabs(g->origin[a])), MG_CELL);
-    }
-    double ta = 0.0, Eta = 0.0;
+    citer_t it;
+    citer_init(&it, g, X, w, &mc);
     int mp = o->max_probes_per_cell < 1 || o->max_probes_per_cell > 8 ? 8 : o->max_probes_per_cell;
     int ordinal = 0;
-    while (ta < tfar && tfar > 0) {
+    int cell[3];
+    double ta, Eta, tb, Etb;
+    while (citer_next(&it, &mc, cell, &ta, &Eta, &tb, &Etb)) {
         ++n_cell;
-        /* next interior grid plane along each axis */
-        double tn[3], En[3];
-        for (int a = 0; a < 3; ++a) {
-            tn[a] = INFINITY; En[a] = 0;
-            int pidx = -1;
-            if (w[a] > 0 && cell[a] + 1 <= cell_max(g, a)) pidx = cell[a] + 1;
-            else if (w[a] < 0 && cell[a] >= 1) pidx = cell[a];
-            if (pidx >= 0) {
-                double plane = g->origin[a] + pidx * g->spacing[a];
-                tn[a] = (plane - X[a]) / w[a];
-                En[a] = (fabs(plane) + fabs(X[a]) + fabs(tn[a])) / fabs(w[a]);
-            }
-        }
-        double tb = tfar, Etb = Efar;
-        for (int a = 0; a < 3; ++a)
-            if (tn[a] < tb) { tb = tn[a]; Etb = En[a]; }
-        for (int a = 0; a < 3; ++a) {
-            if (!isfinite(tn[a])) continue;
-            decide(&mc, tn[a] - tfar, En[a] + Efar, MG_CELL);
-            for (int b = a + 1; b < 3; ++b)
-                if (isfinite(tn[b])) decide(&mc, tn[a] - tn[b], En[a] + En[b], MG_CELL);
-        }
         const grid_t *cg = L2 && L2->coarse ? (const grid_t *)L2->coarse : NULL;
         int ccell[3] = {0, 0, 0};
         if (cg)
@@ -808,6 +867,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
                         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = idx[k]; out->wts[4 * ri + k] = wt[k]; }
                     if (out->dtdr) out->dtdr[ri] = pr.dtdr;
                     if (out->kink) out->kink[ri] = pr.kink;
+                    if (out->tcond) out->tcond[ri] = pr.tcond;
                     if (out->drgbdt) {
                         double dr[3] = {0, 0, 0};
                         if (!o->nearest && !pr.eye) radiance_dt(G->N, R, pr.dirp, w, dr);
@@ -818,10 +878,6 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
                 if (pr.status == ST_UNKNOWN) any_unknown = 1;
             }
         }
-        if (tb >= tfar) break;
-        for (int a = 0; a < 3; ++a)
-            if (tn[a] == tb) cell[a] += w[a] > 0 ? 1 : -1;
-        ta = tb; Eta = Etb;
         ++ordinal;
     }
     out->status[ri] = (uint8_t)(any_unknown ? ST_UNKNOWN : ST_MISS);
@@ -834,6 +890,7 @@ static void trace_ray(const grid_t *g, const level2_t *L2, const opts_t *o, cons
         for (int k = 0; k < 4; ++k) { out->taps[4 * ri + k] = -1; out->wts[4 * ri + k] = 0; }
     if (out->dtdr) out->dtdr[ri] = 0;
     if (out->kink) out->kink[ri] = 0;
+    if (out->tcond) out->tcond[ri] = 0;
     if (out->drgbdt)
         for (int ch = 0; ch < 3; ++ch) out->drgbdt[3 * ri + ch] = 0;
 done:
@@ -960,3 +1017,37 @@ void oracle_bilinear_taps(double u, double v, int N, int32_t idx[4], double wt[4
 }
 
 double oracle_half_to_double(uint16_t h) { return half_to_double(h); }
+
+/* The grid iterator's walk of one ray: up to cap cells (i, j, k) with their intervals
+ * [ta, tb]; returns the number of cells. */
+int oracle_cell_walk(const grid_t *g, const double X[3], const double win[3], int cap, int32_t *cells, double *tab) {
+    double w[3];
+    double wl = sqrt(win[0] * win[0] + win[1] * win[1] + win[2] * win[2]);
+    for (int a = 0; a < 3; ++a) w[a] = win[a] / wl;
+    citer_t it;
+    citer_init(&it, g, X, w, NULL);
+    int cell[3], cnt = 0;
+    double ta, Eta, tb, Etb;
+    while (citer_next(&it, NULL, cell, &ta, &Eta, &tb, &Etb)) {
+        if (cnt < cap) {
+            for (int a = 0; a < 3; ++a) cells[3 * cnt + a] = cell[a];
+            tab[2 * cnt] = ta;
+            tab[2 * cnt + 1] = tb;
+        }
+        ++cnt;
+    }
+    return cnt;
+}
+
+/* The cage of one cell as the trace visits it: probe indices closest to the eye X first
+ * (ties by corner code); returns how many (8, or every probe of a smaller layout). */
+int oracle_cage_order(const grid_t *g, const int32_t cell[3], const double X[3], int32_t probes[8]) {
+    int cl[3] = {cell[0], cell[1], cell[2]}, code[8];
+    double dd[8];
+    int n = cage_sort(g, cl, X, code, dd);
+    for (int k = 0; k < n; ++k) {
+        int pc[3];
+        probes[k] = cage_probe(g, cl, code[k], pc);
+    }
+    return n;
+}

@@ -418,8 +418,8 @@ class ProbeTraceFn(torch.autograd.Function):
     forward: the FP32 master radiance is rounded to the FP16 storage the trace reads (or
     `storage`, the caller's FP16 rounding of master, is read as it is);
     backward: probe_trace_backward into a zeroed FP32 buffer, passed straight through the
-    FP16 rounding to the master.  keep_hits=True keeps the forward's hit and t outputs (8
-    bytes per ray) and runs probe_trace_backward_hits instead of recomputing the trace."""
+    FP16 rounding to the master.  keep_hits=True keeps the forward's hit and t outputs (12
+    bytes per ray: probe and texel as int32, t as FP32) and runs probe_trace_backward_hits instead of recomputing the trace."""
 
     @staticmethod
     def forward(ctx, master, grid, views, opts=None, keep_hits=False, storage=None):

@@ -17,7 +17,8 @@ from . import PT_FLAG_PERSISTENT, ProbeTraceFn, adam_step, make_views, trace_opt
 class RadianceFit:
     """Adam on FP32 master radiance [P,N,N,3] against target images of the given views.
 
-    keep_hits: the adjoint from the forward's hits (8 bytes per ray) instead of a second
+    keep_hits: the adjoint from the forward's hits (12 bytes per ray: probe and texel as
+    int32, t as FP32) instead of a second
     trace.  optimizer: "fused" (pt_adam_step: moments, master and FP16 storage in one pass)
     or "torch" (torch.optim.Adam, its fused kernel where available)."""
 

@@ -9,7 +9,7 @@ synthetic rooms stand in for them.
 Scene recipe (all lengths relative to the probe spacing ``s``):
 
 * room = [0, dims*s]^3, six inward-facing walls with albedo U[0.1,0.9]^3;
-* probes at the vertices of a uniform grid, ``origin = s/2`` (probe (i,j,k) at
+* one probe on every point of a regular lattice, ``origin = s/2`` (probe (i,j,k) at
   ``origin + (i,j,k)*s``), so every probe is strictly inside the room;
 * K objects, each a box (prob 1/2: centre uniform in the room, two half-extents
   U[0.1,1.5]s and one, on a random axis, U[0.05,0.35]s) or a sphere (radius

@@ -48,28 +48,88 @@ def degenerate_rays(scene, probes, seed=0, n_free=60):
     return np.array(o, np.float32), np.array(d, np.float32), np.array(tag)
 
 
-def hit_is_valid(probes, o, d, status, hit, t, tau, texel_slack=1):
-    """Per ray: a HIT is valid when its point lies in the reported probe's reported texel
-    (within ``texel_slack`` texels) at a radial distance between the stored distance r and
-    r (1 + tau) (the hit is the root rho = r or an entry point with r <= rho <= r (1 + tau)),
-    with an FP32 slack of 1e-4 relative.  Non-HIT rays are valid with t = +inf."""
+def hit_is_valid(probes, o, d, status, hit, t, tau, max_probes=8):
+    """Per ray: whether a reported HIT is one the method can give at an exact tie.
+
+    A HIT of probe p, texel k at distance t is valid when (with FP32 slack: 1e-3 texel in
+    the map, 1e-4 relative in distances, 1e-5 relative in the fire tests):
+    * the hit point lies in texel k of probe p's map, at a radial distance rho between the
+      stored r and r (1 + tau) (the root rho = r, or an entry point behind the surface);
+    * the stored normal of the texel faces the ray (n . w < 0);
+    * p is one of the first ``max_probes`` cage probes of a cell whose interval [ta, tb] of
+      the ray holds t, and in p's flat texel sequence over that interval (double precision)
+      texel k is reached with no earlier texel firing (stored distance below the ray's
+      largest radial distance in it), and k itself fires without a shadow entry
+      (rho_in <= r (1 + tau));
+    * for an eye at the probe (|X - O| <= 1e-6 spacing): t = r and k is the texel of oct(w).
+    Non-HIT rays are valid with t = +inf."""
     import oracle
     N = probes.N
     O = probe_origins(probes.dims, probes.origin, probes.spacing).astype(np.float64)
+    g = oracle.Grid.from_probes(probes)
+    D = probes.distance.reshape(len(O), -1).astype(np.float64)
+    nbits = probes.normal.reshape(len(O), N * N, 2)
+    eye_eps = 1e-6 * float(np.min(probes.spacing))
     ok = np.ones(len(o), bool)
+
+    def texel_of(uv):
+        return (uv + 1.0) * N / 2.0
+
+    def in_texel(uv, k, slack=1e-3):
+        ti, tj = texel_of(uv)
+        ki, kj = k % N, k // N
+        return ki - slack <= ti <= ki + 1 + slack and kj - slack <= tj <= kj + 1 + slack
+
     for i in np.nonzero(status == oracle.HIT)[0]:
         p, k = int(hit[i, 0]), int(hit[i, 1])
-        q = o[i].astype(np.float64) + float(t[i]) * d[i].astype(np.float64) - O[p]
-        rho = np.linalg.norm(q)
-        r = float(probes.distance[p].ravel()[k])
-        if rho < 1e-9:
+        if not (0 <= p < len(O) and 0 <= k < N * N):
             ok[i] = False
             continue
-        uv = oracle.oct_encode(q)
-        ti, tj = (uv + 1) * N / 2
-        ki, kj = k % N, k // N
-        near = (ki - texel_slack - 1e-3 <= ti <= ki + 1 + texel_slack + 1e-3 and
-                kj - texel_slack - 1e-3 <= tj <= kj + 1 + texel_slack + 1e-3)
-        ok[i] = near and (r * (1 - 1e-4) <= rho <= r * (1 + tau) * (1 + 1e-4))
+        X = o[i].astype(np.float64)
+        w = d[i].astype(np.float64)
+        w /= np.linalg.norm(w)
+        Xp = X - O[p]
+        r = D[p, k]
+        ti = float(t[i])
+        nuv = np.array([oracle.half_to_double(int(b)) for b in nbits[p, k]])
+        nrm = oracle.oct_decode(nuv)
+        if not np.dot(nrm, w) < 1e-6:
+            ok[i] = False
+            continue
+        if np.linalg.norm(Xp) <= eye_eps * (1 + 1e-3):
+            ok[i] = abs(ti - r) <= 1e-4 * r and in_texel(oracle.oct_encode(w), k)
+            continue
+        q = Xp + ti * w
+        rho = np.linalg.norm(q)
+        if rho < 1e-9 or not in_texel(oracle.oct_encode(q), k):
+            ok[i] = False
+            continue
+        if not (r * (1 - 1e-4) <= rho <= r * (1 + tau) * (1 + 1e-4)):
+            ok[i] = False
+            continue
+        # the cells whose interval holds t and whose cage holds p (first max_probes of them)
+        cells, tab = oracle.cell_walk(g, X, w)
+        first_ok = False
+        for c, (ta, tb) in zip(cells, tab):
+            if not (ta - 1e-5 * max(1.0, ti) <= ti <= tb + 1e-5 * max(1.0, ti)):
+                continue
+            if p not in oracle.cage_order(g, c, X)[:max_probes]:
+                continue
+            ij, tio, _ = oracle.texel_sequence(N, Xp, w, ta, tb)
+            kk = ij[:, 1] * N + ij[:, 0]
+            rin = np.linalg.norm(Xp[None, :] + tio[:, 0:1] * w[None, :], axis=1)
+            rout = np.linalg.norm(Xp[None, :] + tio[:, 1:2] * w[None, :], axis=1)
+            rmax = np.maximum(rin, rout)
+            fires_clearly = D[p, kk] < rmax * (1 - 1e-5)
+            may_fire = D[p, kk] < rmax * (1 + 1e-5)
+            for m in np.nonzero(kk == k)[0]:
+                if fires_clearly[:m].any():
+                    break  # an earlier texel fires: the march stops before k
+                if may_fire[m] and rin[m] <= r * (1 + tau) * (1 + 1e-5):
+                    first_ok = True
+                    break
+            if first_ok:
+                break
+        ok[i] = first_ok
     ok[status != oracle.HIT] = ~np.isfinite(t[status != oracle.HIT])
     return ok

@@ -2,8 +2,9 @@
 directions, rays through probe centres, rays on cell planes, rays from probe centres.
 These are the exact ties the float margin exists for, so more of them may disagree than in
 a random frame: every disagreeing ray must be in the oracle's margin, at most 0.5% may
-disagree, and every HIT the GPU reports must be valid (its point in the reported texel at
-a radial distance between r and r(1 + tau))."""
+disagree, and every HIT the GPU reports must be valid (tests/degenerate.py: the hit point
+in the reported texel at a radial distance between r and r(1 + tau), the stored normal
+facing the ray, and the texel the first to fire in the probe's traced interval)."""
 import numpy as np
 import pytest
 import torch
@@ -32,7 +33,7 @@ def test_degenerate_rays(name, kw, seed):
     info = {k: v for k, v in s.items() if k != "disagree_idx"}
     print(f"[degenerate] {name} seed {seed}: {info}", flush=True)
     assert s["disagree_outside_margin"] == 0, info
-    assert s["disagree"] <= 0.01 * s["n"], info
+    assert s["disagree"] <= 0.005 * s["n"], info
     valid = hit_is_valid(probes, o, d, res["status"], res["hit"], res["t"], 8.0 / probes.N)
     assert valid.all(), (np.nonzero(~valid)[0][:10], tag[~valid][:10])
     assert (res["status"] == orc["status"]).mean() >= 0.995

@@ -129,10 +129,12 @@ def test_differentiable_grid_all_views_both_adjoints_sampled(diff_grid):
     assert_parity(s, "diff grid, 32 views persistent, 32k sampled rays")
     g_s = rng.normal(size=(len(sel), 3)).astype(np.float32).astype(np.float64)
     g_s[s["disagree_idx"]] = 0.0
-    # a ray whose hit distance is ill-conditioned (near-tangent root, flagged by the oracle)
+    # a ray whose hit distance is ill-conditioned (flagged by the oracle, or a condition scale
+    # above 100 t, or a near-tangent root with dt/dr >= 100)
     # has an equally ill-conditioned sample direction, so its bilinear weights are not held
     # to the FP32 bound: it gets no upstream gradient (as in the distance adjoint's test)
-    ill = (orc["margin"] & oracle.MG_THIT) != 0
+    hit_o = orc["status"] == oracle.HIT
+    ill = ((orc["margin"] & oracle.MG_THIT) != 0) | (hit_o & ((orc["tcond"] > 100 * orc["t"]) | (orc["dtdr"] >= 100)))
     g_s[ill] = 0.0
     print(f"[grad] diff grid 32 views: {int(ill.sum())} rays with an ill-conditioned hit distance left out",
           flush=True)

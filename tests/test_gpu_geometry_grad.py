@@ -8,7 +8,8 @@ probe and where the four taps' terms cancel; the device code built for the host 
 4e-4 at most, and 2e-4 on dt/dr for grazing roots.)  Left out on both sides (zero upstream
 gradient): rays whose
 classification differs between GPU and oracle (all inside the float margin, checked by the
-forward parity tests), rays with an ill-conditioned hit distance (near-tangent root), rays
+forward parity tests), rays with an ill-conditioned hit distance (condition scale above
+100 t, or a near-tangent root with dt/dr >= 100), rays
 within the margin of switching between the entry-point hit and the root (dt/dr jumps from
 0 there), and
 rays whose radiance sample sits within 1e-4 texel of a texel-centre line or within 1e-5 of
@@ -61,7 +62,11 @@ def _check(pt, probes, views, grid, rad, og, use_rgb=True, use_t=True, opts=None
     hit = orc["status"] == oracle.HIT
     keep = np.ones(n, bool)
     keep[s["disagree_idx"]] = False
+    # rays whose hit distance or its derivative FP32 cannot resolve to this tolerance: flagged
+    # by the oracle, an entry crossing with a condition scale above 100 t, or a near-tangent
+    # root (dt/dr = r / sqrt(r^2 - d_perp^2) >= 100)
     keep &= (orc["margin"] & oracle.MG_THIT) == 0
+    keep &= ~hit | ((orc["tcond"] <= 100 * orc["t"]) & (orc["dtdr"] < 100))
     keep &= orc["kink"] == 0  # entry point vs root within the margin: dt/dr jumps there
     wts = orc["wts"]
     fx, fy = wts[:, 1] + wts[:, 3], wts[:, 2] + wts[:, 3]
