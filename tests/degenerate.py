@@ -48,6 +48,63 @@ def degenerate_rays(scene, probes, seed=0, n_free=60):
     return np.array(o, np.float32), np.array(d, np.float32), np.array(tag)
 
 
+def _sideways(w, h):
+    """The zero shift, then 16 shifts of length h perpendicular to w (evenly around it)."""
+    a = np.zeros(3)
+    a[int(np.argmin(np.abs(w)))] = 1.0
+    e1 = a - np.dot(a, w) * w
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(w, e1)
+    yield np.zeros(3)
+    for m in range(16):
+        ang = 2.0 * np.pi * m / 16.0
+        yield h * (np.cos(ang) * e1 + np.sin(ang) * e2)
+
+
+def _first_fire_ok(g, probes, D, p, k, X, w, ti, r, tau, max_probes):
+    """Whether the ray (X, w) can report probe p, texel k at distance ti: the hit point in
+    texel k, and some cell whose interval holds ti (for a ray moving inside a cell plane, a
+    cell on either side) has p among its first max_probes cage probes, with k reached in
+    p's flat texel sequence over that interval (double precision) with no earlier texel
+    firing clearly, and k itself firing without a shadow entry."""
+    import oracle
+    N = probes.N
+    O = probe_origins(probes.dims, probes.origin, probes.spacing).astype(np.float64)
+    Xp = X - O[p]
+    uv = oracle.oct_encode(Xp + ti * w)
+    ui, vj = (uv + 1.0) * N / 2.0
+    ki, kj = k % N, k // N
+    if not (ki - 1e-3 <= ui <= ki + 1 + 1e-3 and kj - 1e-3 <= vj <= kj + 1 + 1e-3):
+        return False
+    walks = [oracle.cell_walk(g, X, w)]
+    for a in range(3):
+        q = (X[a] - probes.origin[a]) / probes.spacing[a]
+        if abs(w[a]) < 1e-6 and abs(q - round(q)) < 1e-5:
+            for sgn in (-1.0, 1.0):
+                Xa = X.copy()
+                Xa[a] += sgn * 1e-4 * probes.spacing[a]
+                walks.append(oracle.cell_walk(g, Xa, w))
+    for cells, tab in walks:
+        for c, (ta, tb) in zip(cells, tab):
+            if not (ta - 1e-5 * max(1.0, ti) <= ti <= tb + 1e-5 * max(1.0, ti)):
+                continue
+            if p not in oracle.cage_order(g, c, X)[:max_probes]:
+                continue
+            ij, tio, _ = oracle.texel_sequence(N, Xp, w, ta, tb)
+            kk = ij[:, 1] * N + ij[:, 0]
+            rin = np.linalg.norm(Xp[None, :] + tio[:, 0:1] * w[None, :], axis=1)
+            rout = np.linalg.norm(Xp[None, :] + tio[:, 1:2] * w[None, :], axis=1)
+            rmax = np.maximum(rin, rout)
+            fires_clearly = D[p, kk] < rmax * (1 - 1e-5)
+            may_fire = D[p, kk] < rmax * (1 + 1e-5)
+            for m in np.nonzero(kk == k)[0]:
+                if fires_clearly[:m].any():
+                    break  # an earlier texel fires: the march stops before k
+                if may_fire[m] and rin[m] <= r * (1 + tau) * (1 + 1e-5):
+                    return True
+    return False
+
+
 def hit_is_valid(probes, o, d, status, hit, t, tau, max_probes=8):
     """Per ray: whether a reported HIT is one the method can give at an exact tie.
 
@@ -57,10 +114,12 @@ def hit_is_valid(probes, o, d, status, hit, t, tau, max_probes=8):
       stored r and r (1 + tau) (the root rho = r, or an entry point behind the surface);
     * the stored normal of the texel faces the ray (n . w < 0);
     * p is one of the first ``max_probes`` cage probes of a cell whose interval [ta, tb] of
-      the ray holds t, and in p's flat texel sequence over that interval (double precision)
-      texel k is reached with no earlier texel firing (stored distance below the ray's
-      largest radial distance in it), and k itself fires without a shadow entry
-      (rho_in <= r (1 + tau));
+      the ray holds t (for a ray moving inside a cell plane, a cell on either side), and
+      in p's flat texel sequence over that interval (double precision) texel k is reached
+      with no earlier texel firing (stored distance below the ray's largest radial distance
+      in it), and k itself fires without a shadow entry (rho_in <= r (1 + tau)); at an
+      exact tie of the texel sequence, for the ray itself or the ray moved sideways by
+      1e-6 spacing in one of 16 directions around it;
     * for an eye at the probe (|X - O| <= 1e-6 spacing): t = r and k is the texel of oct(w).
     Non-HIT rays are valid with t = +inf."""
     import oracle
@@ -99,37 +158,15 @@ def hit_is_valid(probes, o, d, status, hit, t, tau, max_probes=8):
         if np.linalg.norm(Xp) <= eye_eps * (1 + 1e-3):
             ok[i] = abs(ti - r) <= 1e-4 * r and in_texel(oracle.oct_encode(w), k)
             continue
-        q = Xp + ti * w
-        rho = np.linalg.norm(q)
-        if rho < 1e-9 or not in_texel(oracle.oct_encode(q), k):
+        # At an exact tie (a ray inside an axis plane through the probe projects onto a
+        # texel boundary line, on the lower hemisphere onto the fold of the square's edge; a
+        # ray through a texel corner) the texels on every side of the tie are valid: if the
+        # ray itself does not validate the hit, the same ray moved sideways by 1e-6 spacing
+        # in 16 directions around it is tried.
+        if not (r * (1 - 1e-4) <= np.linalg.norm(Xp + ti * w) <= r * (1 + tau) * (1 + 1e-4)):
             ok[i] = False
             continue
-        if not (r * (1 - 1e-4) <= rho <= r * (1 + tau) * (1 + 1e-4)):
-            ok[i] = False
-            continue
-        # the cells whose interval holds t and whose cage holds p (first max_probes of them)
-        cells, tab = oracle.cell_walk(g, X, w)
-        first_ok = False
-        for c, (ta, tb) in zip(cells, tab):
-            if not (ta - 1e-5 * max(1.0, ti) <= ti <= tb + 1e-5 * max(1.0, ti)):
-                continue
-            if p not in oracle.cage_order(g, c, X)[:max_probes]:
-                continue
-            ij, tio, _ = oracle.texel_sequence(N, Xp, w, ta, tb)
-            kk = ij[:, 1] * N + ij[:, 0]
-            rin = np.linalg.norm(Xp[None, :] + tio[:, 0:1] * w[None, :], axis=1)
-            rout = np.linalg.norm(Xp[None, :] + tio[:, 1:2] * w[None, :], axis=1)
-            rmax = np.maximum(rin, rout)
-            fires_clearly = D[p, kk] < rmax * (1 - 1e-5)
-            may_fire = D[p, kk] < rmax * (1 + 1e-5)
-            for m in np.nonzero(kk == k)[0]:
-                if fires_clearly[:m].any():
-                    break  # an earlier texel fires: the march stops before k
-                if may_fire[m] and rin[m] <= r * (1 + tau) * (1 + 1e-5):
-                    first_ok = True
-                    break
-            if first_ok:
-                break
-        ok[i] = first_ok
+        ok[i] = any(_first_fire_ok(g, probes, D, p, k, X + e, w, ti, r, tau, max_probes)
+                    for e in _sideways(w, 1e-6 * float(np.min(probes.spacing))))
     ok[status != oracle.HIT] = ~np.isfinite(t[status != oracle.HIT])
     return ok

