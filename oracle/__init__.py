@@ -51,7 +51,14 @@ class _Opts(ctypes.Structure):
     _fields_ = [("thickness_rel", ctypes.c_double), ("eye_eps_rel", ctypes.c_double),
                 ("background", ctypes.c_double * 3), ("delta", ctypes.c_double),
                 ("max_probes_per_cell", ctypes.c_int32), ("check_hier", ctypes.c_int32),
-                ("top_level", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("nearest", ctypes.c_int32)]
+                ("top_level", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("nearest", ctypes.c_int32),
+                ("soft", ctypes.c_int32)]
+
+
+class _SoftOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("count", "probe", "texel", "a", "t", "rin", "rk", "c", "taps", "wts", "dtdr", "drgbdt", "rgb",
+                 "trans", "margin")]
 
 
 class _Out(ctypes.Structure):
@@ -94,6 +101,10 @@ def _load():
         lib.oracle_cell_walk.restype = ctypes.c_int
         lib.oracle_cage_order.argtypes = [ctypes.POINTER(_Grid), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_cage_order.restype = ctypes.c_int
+        lib.oracle_trace_soft.argtypes = [ctypes.POINTER(_Grid), ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                          ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.POINTER(_SoftOut)]
+        lib.oracle_trace_soft.restype = ctypes.c_int
         lib.oracle_half_to_double.argtypes = [ctypes.c_uint16]
         lib.oracle_half_to_double.restype = ctypes.c_double
         _lib = lib
@@ -213,7 +224,8 @@ def view_rays(pos, right, up, fwd, tan_half_fov_y, width, height, pixels=None):
 # ---------------------------------------------------------------------------------------------
 def default_opts(N: int, **kw) -> dict:
     o = dict(thickness_rel=8.0 / N, eye_eps_rel=1e-6, background=(0.0, 0.0, 0.0), delta=DEFAULT_DELTA,
-             max_probes_per_cell=8, check_hier=1, top_level=-1, nthreads=os.cpu_count() or 1, nearest=False)
+             max_probes_per_cell=8, check_hier=1, top_level=-1, nthreads=os.cpu_count() or 1, nearest=False,
+             soft=False)
     o.update(kw)
     return o
 
@@ -242,6 +254,7 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) 
     oo.top_level = int(opts["top_level"])
     oo.nthreads = int(opts["nthreads"])
     oo.nearest = int(bool(opts["nearest"]))
+    oo.soft = int(bool(opts["soft"]))
     res = dict(status=np.empty(n, np.uint8), t=np.empty(n, np.float64), rgb=np.empty((n, 3), np.float64),
                probe=np.empty(n, np.int32), texel=np.empty(n, np.int32), margin=np.empty(n, np.int32),
                tests=np.empty(n, np.int32), normals=np.empty(n, np.int32), flat_tests=np.empty(n, np.int32),
@@ -266,6 +279,105 @@ def trace(grid: Grid, origins: np.ndarray, dirs: np.ndarray, coarse=None, **kw) 
         lib.oracle_trace2(ctypes.byref(g), ctypes.byref(L2), ctypes.byref(oo), n, _ptr(o), _ptr(d),
                           ctypes.byref(out))
     return res
+
+
+def trace_soft(grid: Grid, origins: np.ndarray, dirs: np.ndarray, sigma: float, coarse=None, kcap: int = 64,
+               **kw) -> dict:
+    """Soft visibility (an extension; the paper's classification is hard): every probe trace
+    whose first firing texel faces the ray is a candidate j, in walk order, accepted with
+    weight a_j = logistic((r_j (1 + tau) - rho_in,j) / (sigma r_j)); the colour is
+    sum_j a_j prod_{i<j} (1 - a_i) c_j + prod_j (1 - a_j) background, the walk stopping once
+    the remaining weight is <= 1e-6.  Returns per-ray arrays: count [n] (-1: more than kcap
+    candidates), per-candidate probe/texel/a/t/rin/rk/dtdr [n,kcap], c/drgbdt [n,kcap,3],
+    taps/wts [n,kcap,4], and rgb [n,3], trans [n] (weight of the background), margin [n]."""
+    lib = _load()
+    o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    opts = default_opts(grid.N, **kw)
+    opts["soft"] = True
+    oo = _Opts()
+    oo.thickness_rel = float(opts["thickness_rel"])
+    oo.eye_eps_rel = float(opts["eye_eps_rel"])
+    oo.background[:] = [float(c) for c in opts["background"]]
+    oo.delta = float(opts["delta"])
+    oo.max_probes_per_cell = int(opts["max_probes_per_cell"])
+    oo.check_hier = 0
+    oo.top_level = int(opts["top_level"])
+    oo.nthreads = int(opts["nthreads"])
+    oo.nearest = int(bool(opts["nearest"]))
+    oo.soft = 1
+    K = int(kcap)
+    res = dict(count=np.empty(n, np.int32), probe=np.full((n, K), -1, np.int32), texel=np.full((n, K), -1, np.int32),
+               a=np.zeros((n, K)), t=np.zeros((n, K)), rin=np.zeros((n, K)), rk=np.zeros((n, K)),
+               c=np.zeros((n, K, 3)), taps=np.zeros((n, K, 4), np.int32), wts=np.zeros((n, K, 4)),
+               dtdr=np.zeros((n, K)), drgbdt=np.zeros((n, K, 3)), rgb=np.empty((n, 3)), trans=np.empty(n),
+               margin=np.empty(n, np.int32))
+    out = _SoftOut()
+    for k, v in res.items():
+        setattr(out, k, v.ctypes.data)
+    g = grid._struct()
+    L2 = None
+    if coarse is not None:
+        cgrid, off, ratio = coarse
+        cs = cgrid._struct()
+        L2 = _Level2()
+        L2.coarse = ctypes.addressof(cs)
+        L2.plane_off[:] = [int(x) for x in off]
+        L2.ratio[:] = [int(x) for x in ratio]
+    rc = lib.oracle_trace_soft(ctypes.byref(g), ctypes.byref(L2) if L2 is not None else None, ctypes.byref(oo),
+                               float(sigma), K, n, _ptr(o), _ptr(d), ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("oracle_trace_soft: sigma must be > 0 and kcap >= 1")
+    res["sigma"] = float(sigma)
+    res["tau"] = float(opts["thickness_rel"])
+    res["background"] = np.asarray(opts["background"], dtype=np.float64)
+    return res
+
+
+def vjp_soft(grid, result: dict, grad_rgb: np.ndarray):
+    """Adjoint of trace_soft's colour (an extension beyond the paper): gradients with respect
+    to the stored distances [P,N,N] and the radiance [P,N,N,3], the fire tests and the
+    candidates held.  With w_j = a_j prod_{i<j} (1 - a_i), A_j = sum_{k<=j} w_k c_k and g the
+    upstream gradient of rgb:
+        dL/dx_j   = g . (w_j (1 - a_j) c_j - a_j (rgb - A_j))       (x_j the logistic's argument)
+        dL/dr_j  += dL/dx_j * rho_in,j / (sigma r_j^2) + w_j (g . dc_j/dt) dt_j/dr_j
+        dL/dRad  += w_j * bilinear weight * g at each of candidate j's taps.
+    Accumulated in double."""
+    grids = grid if isinstance(grid, (list, tuple)) else (grid,)  # (fine, coarse): probes concatenated
+    P = sum(gr.distance.shape[0] for gr in grids)
+    N = grids[0].N
+    gd = np.zeros(P * N * N, dtype=np.float64)
+    grad = np.zeros((P * N * N, 3), dtype=np.float64)
+    if np.any(result["count"] < 0):
+        raise ValueError("vjp_soft: a ray needed more candidates than kcap")
+    g = np.asarray(grad_rgb, dtype=np.float64).reshape(-1, 3)
+    rgb = result["rgb"]
+    sigma = result["sigma"]
+    n, K = result["a"].shape
+    Pj = np.ones(n)
+    A = np.zeros((n, 3))
+    for j in range(K):
+        on = result["count"] > j
+        if not on.any():
+            break
+        a = result["a"][on, j]
+        c = result["c"][on, j]
+        wj = a * Pj[on]
+        A[on] += wj[:, None] * c
+        dx = np.einsum("ij,ij->i", g[on], wj[:, None] * (1.0 - a)[:, None] * c - a[:, None] * (rgb[on] - A[on]))
+        rk = result["rk"][on, j]
+        rin = result["rin"][on, j]
+        dxdr = np.where(rk > 0.0, rin / (sigma * np.where(rk > 0.0, rk, 1.0) ** 2), 0.0)
+        geo = wj * np.einsum("ij,ij->i", g[on], result["drgbdt"][on, j]) * result["dtdr"][on, j]
+        geo = np.where(wj != 0.0, geo, 0.0)  # dt/dr may be infinite at tangency, where w_j = 0
+        flat = result["probe"][on, j].astype(np.int64) * (N * N) + result["texel"][on, j]
+        np.add.at(gd, flat, dx * dxdr + geo)
+        taps = result["probe"][on, j].astype(np.int64)[:, None] * (N * N) + result["taps"][on, j]
+        for k in range(4):
+            np.add.at(grad, taps[:, k], (wj * result["wts"][on, j, k])[:, None] * g[on])
+        Pj[on] *= 1.0 - a
+    return gd.reshape(P, N, N), grad.reshape(P, N, N, 3)
 
 
 def trace_view(grid: Grid, view, pixels=None, **kw) -> dict:

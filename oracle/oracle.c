@@ -97,6 +97,9 @@ typedef struct {
     int32_t nearest;       /* radiance of the hit texel itself (the appendix algorithms fetch
                               the colour of the texel the march stopped at) instead of the
                               bilinear sample at the hit direction */
+    int32_t soft;          /* soft visibility (oracle_trace_soft): a probe whose first firing
+                              texel faces the ray is a candidate also when the ray entered
+                              that texel behind the stored surface */
 } opts_t;
 
 /* Two-level probe hierarchy (the paper's hierarchical scene representation; no algorithm
@@ -520,6 +523,9 @@ typedef struct {
     int kink;       /* bit 0: rho_in within the margin of r (entry point vs root) */
     double tcond;   /* condition scale of t (entry crossing, or the root) */
     int tests, normals, flat_tests, pieces;
+    int cand;       /* soft visibility: the first firing texel faces the ray (HIT, or UNKNOWN by
+                       the shadow entry only); t, dirp and dtdr are then set */
+    double rin, rk; /* rho at the firing texel's entry and its stored distance */
 } presult_t;
 
 /* traceOneProbe over [ta, tb] */
@@ -568,6 +574,9 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
             res->t = rk;
             res->dtdr = 1.0;
             res->eye = 1;
+            res->cand = 1;
+            res->rk = rk;
+            res->rin = 0.0; /* the ray starts at the probe: it cannot enter behind the surface */
             memcpy(res->dirp, w, sizeof(double) * 3);
         }
         return;
@@ -615,7 +624,10 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
         res->texel = k;
         double thr = rk * (1.0 + o->thickness_rel);
         decide(mc, ff.rin - thr, rk + r.S + fabs(ff.tin) + drho_at(&r, ff.tin) * ff.Ein, MG_CLASS);
-        if (ff.rin > thr) {
+        const int shadow = ff.rin > thr;
+        res->rk = rk;
+        res->rin = ff.rin;
+        if (shadow && !o->soft) {
             res->status = ST_UNKNOWN; /* the ray entered the texel behind the stored surface */
             return;
         }
@@ -629,7 +641,8 @@ static void trace_one_probe(const grid_t *g, const opts_t *o, int p, const doubl
             res->status = ST_UNKNOWN;
             return;
         }
-        res->status = ST_HIT;
+        res->cand = 1;
+        res->status = shadow ? ST_UNKNOWN : ST_HIT;
         /* hit distance: entry point if already at/behind the surface, else where rho = r */
         double th;
         if (fabs(ff.rin - rk) <= mc->delta * (rk + r.S + fabs(ff.tin) + drho_at(&r, ff.tin) * ff.Ein)) res->kink |= 1;
@@ -904,6 +917,170 @@ done:
         out->work[3 * ri + 1] = n_piece;
         out->work[3 * ri + 2] = n_cell;
     }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Soft visibility (an extension; the paper's classification is hard).  The hard method
+ * takes the first probe trace, in walk order, whose first firing texel faces the ray and
+ * was entered no more than the thickness behind the stored surface.  The relaxation keeps
+ * every probe trace whose first firing texel faces the ray as a candidate j, accepted with
+ * weight a_j = logistic(x_j), x_j = (r_j (1 + tau) - rho_in,j) / (sigma r_j) (0 if r_j <= 0):
+ *     rgb = sum_j a_j prod_{i<j} (1 - a_i) c_j + prod_j (1 - a_j) background,
+ * with c_j the radiance sample at candidate j's hit point (the hard rule's point: the
+ * entry point when rho_in >= r, else where rho = r).  As sigma -> 0 the weights become the
+ * hard decision.  The walk stops once the remaining weight prod (1 - a) is <= 1e-6, or at
+ * its end; the fire tests and the march are those of the hard method.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t *count;   /* [n] candidates recorded; -1 if more than kcap were needed */
+    int32_t *probe;   /* [n][kcap] probe (coarse probes after the fine ones) */
+    int32_t *texel;   /* [n][kcap] first firing level-0 texel j*N+i */
+    double *a;        /* [n][kcap] acceptance weight */
+    double *t;        /* [n][kcap] hit distance of the candidate */
+    double *rin;      /* [n][kcap] rho at the texel's entry */
+    double *rk;       /* [n][kcap] stored distance of the texel */
+    double *c;        /* [n][kcap][3] radiance sample */
+    int32_t *taps;    /* [n][kcap][4] bilinear taps (texel indices of the candidate's probe) */
+    double *wts;      /* [n][kcap][4] their weights */
+    double *dtdr;     /* [n][kcap] d t / d r with the candidate's texel and case held */
+    double *drgbdt;   /* [n][kcap][3] d c / d t */
+    double *rgb;      /* [n][3] the soft colour */
+    double *trans;    /* [n] remaining weight (of the background) */
+    int32_t *margin;  /* [n] margin bits of the decisions taken (fire tests, walk, normals) */
+} soft_out_t;
+
+#define SOFT_STOP 1e-6
+
+static void trace_ray_soft(const grid_t *g, const level2_t *L2, const opts_t *o, double sigma, int kcap,
+                           const double X[3], const double win[3], soft_out_t *out, int64_t ri) {
+    double w[3];
+    double wl = sqrt(win[0] * win[0] + win[1] * win[1] + win[2] * win[2]);
+    for (int a = 0; a < 3; ++a) w[a] = win[a] / wl;
+    mctx_t mc;
+    mc.bits = 0;
+    mc.score = INFINITY;
+    mc.delta = o->delta;
+    citer_t it;
+    citer_init(&it, g, X, w, &mc);
+    int mp = o->max_probes_per_cell < 1 || o->max_probes_per_cell > 8 ? 8 : o->max_probes_per_cell;
+    int cell[3];
+    double ta, Eta, tb, Etb;
+    double T = 1.0, rgb[3] = {0, 0, 0};
+    int n = 0, overflow = 0;
+    const int64_t K = kcap;
+    while (T > SOFT_STOP && citer_next(&it, &mc, cell, &ta, &Eta, &tb, &Etb)) {
+        const grid_t *cg = L2 && L2->coarse ? (const grid_t *)L2->coarse : NULL;
+        int ccell[3] = {0, 0, 0};
+        if (cg)
+            for (int a = 0; a < 3; ++a)
+                ccell[a] = clampi(floordiv(cell[a] - L2->plane_off[a], L2->ratio[a]), 0, cell_max(cg, a));
+        const int Pf = g->dims[0] * g->dims[1] * g->dims[2];
+        for (int lev = 0; lev < (cg ? 2 : 1) && T > SOFT_STOP; ++lev) {
+            const grid_t *G = lev == 0 ? g : cg;
+            const int *cl = lev == 0 ? cell : ccell;
+            int code[8];
+            double dd[8];
+            int ncage = cage_sort(G, cl, X, code, dd);
+            int mpc = mp < ncage ? mp : ncage;
+            for (int rk = 0; rk < mpc && T > SOFT_STOP; ++rk) {
+                int pc[3];
+                int p = cage_probe(G, cl, code[rk], pc);
+                presult_t pr;
+                trace_one_probe(G, o, p, X, w, ta, tb, Eta, Etb, &mc, &pr);
+                if (!pr.cand) continue;
+                if (n == kcap) {
+                    overflow = 1;
+                    T = 0.0;
+                    break;
+                }
+                double x = pr.rk > 0.0 ? (pr.rk * (1.0 + o->thickness_rel) - pr.rin) / (sigma * pr.rk) : -INFINITY;
+                double acc = 1.0 / (1.0 + exp(-x));
+                int idx[4];
+                double wt[4];
+                if (o->nearest) {
+                    for (int k = 0; k < 4; ++k) { idx[k] = pr.texel; wt[k] = k == 0 ? 1.0 : 0.0; }
+                } else {
+                    double uv[2];
+                    oracle_oct_encode(pr.dirp, uv);
+                    bilinear_taps(uv[0], uv[1], G->N, idx, wt);
+                }
+                const float *R = G->rad + (int64_t)p * G->N * G->N * 3;
+                double c[3], dr[3] = {0, 0, 0};
+                for (int ch = 0; ch < 3; ++ch) {
+                    c[ch] = 0;
+                    for (int k = 0; k < 4; ++k) c[ch] += wt[k] * (double)R[3 * idx[k] + ch];
+                }
+                if (!o->nearest && !pr.eye) radiance_dt(G->N, R, pr.dirp, w, dr);
+                const int64_t q = ri * K + n;
+                out->probe[q] = lev == 0 ? p : Pf + p;
+                out->texel[q] = pr.texel;
+                out->a[q] = acc;
+                out->t[q] = pr.t;
+                out->rin[q] = pr.rin;
+                out->rk[q] = pr.rk;
+                out->dtdr[q] = pr.dtdr;
+                for (int ch = 0; ch < 3; ++ch) {
+                    out->c[3 * q + ch] = c[ch];
+                    out->drgbdt[3 * q + ch] = dr[ch];
+                    rgb[ch] += T * acc * c[ch];
+                }
+                for (int k = 0; k < 4; ++k) {
+                    out->taps[4 * q + k] = idx[k];
+                    out->wts[4 * q + k] = wt[k];
+                }
+                T *= 1.0 - acc;
+                ++n;
+            }
+        }
+    }
+    if (overflow) T = 0.0;
+    out->count[ri] = overflow ? -1 : n;
+    for (int ch = 0; ch < 3; ++ch) out->rgb[3 * ri + ch] = rgb[ch] + T * o->background[ch];
+    out->trans[ri] = T;
+    out->margin[ri] = mc.bits;
+}
+
+typedef struct {
+    const grid_t *g;
+    const level2_t *L2;
+    const opts_t *o;
+    double sigma;
+    int kcap;
+    const double *orig, *dir;
+    int64_t n;
+    soft_out_t *out;
+    atomic_long next;
+} soft_job_t;
+
+static void *soft_worker(void *arg) {
+    soft_job_t *jb = (soft_job_t *)arg;
+    for (;;) {
+        int64_t b = atomic_fetch_add(&jb->next, 256);
+        if (b >= jb->n) break;
+        int64_t e = b + 256 < jb->n ? b + 256 : jb->n;
+        for (int64_t i = b; i < e; ++i)
+            trace_ray_soft(jb->g, jb->L2, jb->o, jb->sigma, jb->kcap, jb->orig + 3 * i, jb->dir + 3 * i, jb->out, i);
+    }
+    return NULL;
+}
+
+/* Soft-visibility candidates and colour of n rays (o->soft must be set); L2 nullable. */
+int oracle_trace_soft(const grid_t *g, const level2_t *L2, const opts_t *o, double sigma, int kcap, int64_t n,
+                      const double *orig, const double *dir, soft_out_t *out) {
+    if (!(sigma > 0.0) || kcap < 1 || !o->soft) return -1;
+    int nt = o->nthreads < 1 ? 1 : (o->nthreads > 256 ? 256 : o->nthreads);
+    soft_job_t jb;
+    jb.g = g; jb.L2 = L2; jb.o = o; jb.sigma = sigma; jb.kcap = kcap;
+    jb.orig = orig; jb.dir = dir; jb.n = n; jb.out = out;
+    atomic_init(&jb.next, 0);
+    if (nt == 1) {
+        soft_worker(&jb);
+        return 0;
+    }
+    pthread_t th[256];
+    for (int i = 0; i < nt; ++i) pthread_create(&th[i], NULL, soft_worker, &jb);
+    for (int i = 0; i < nt; ++i) pthread_join(th[i], NULL);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------------------
