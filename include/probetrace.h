@@ -196,6 +196,26 @@ pt_status probe_trace(const pt_grid *grid, const uint16_t *radiance_dev, const p
                       float *rgb_dev, float *t_dev, uint8_t *status_dev, int32_t *hit_dev, const pt_trace_opts *opts,
                       void *stream);
 
+/* probe_trace for callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same per-view launches
+ * and outputs, bit for bit, with the library's scratch (each view's cage-order tables) in
+ * a fixed 1 MiB device array instead of buffers it allocates.  The array is resolved per
+ * device when a grid is created there, and each GPU keeps it until the process ends.
+ * Arguments, layouts and ownership as for probe_trace.  The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *   - per-view launches only: opts->flags PT_FLAG_PERSISTENT or PT_FLAG_GRAPH is
+ *     UNSUPPORTED (those launch forms use the library's own view table and tile counter);
+ *   - the grid may have at most 262,144 cells, both levels of a hierarchy together
+ *     ((nx-1)(ny-1)(nz-1) of each grid; a layout of fewer than 8 probes counts 1);
+ *     larger grids are INVALID_ARGUMENT;
+ *   - every call on one GPU shares that GPU's array, and every table is rewritten before
+ *     it is read (nothing needs clearing); calls that overlap on one GPU (other streams,
+ *     other threads) race on it, so the caller orders them.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP. */
+pt_status probe_trace_noalloc(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
+                              int32_t n_views, float *rgb_dev, float *t_dev, uint8_t *status_dev, int32_t *hit_dev,
+                              const pt_trace_opts *opts, void *stream);
+
 /* Trace arbitrary rays: origins_dev and dirs_dev are [n][3] FP32 (directions need not be
  * unit length; zero-length directions give MISS).  Outputs as for probe_trace.  n = 0
  * returns PT_OK at once and touches nothing (the buffers may then be NULL); n < 0 is

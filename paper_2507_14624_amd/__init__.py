@@ -28,7 +28,7 @@ PT_FLAG_NO_START_TEXEL = 32
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",
-            "probe_trace", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_hits",
+            "probe_trace", "probe_trace_noalloc", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_hits",
             "probe_trace_backward_distance", "probe_autotune", "pt_adam_step", "pt_last_error")
 
 
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH):
     lib.probe_grid_set_coarse.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.probe_bake_points.argtypes = [ctypes.POINTER(PtGridDesc), vp, vp, vp, i64, vp, vp, vp, vp]
     lib.probe_trace.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_trace_noalloc.argtypes = lib.probe_trace.argtypes
     lib.probe_trace_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_backward.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_autotune.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, ctypes.POINTER(PtTraceOpts), vp]
@@ -87,7 +88,7 @@ def load_library(path: str = LIB_PATH):
     f64 = ctypes.c_double
     lib.pt_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, i32, f64, f64, f64, f64, f64, vp]
     for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
-                 "probe_trace", "probe_trace_rays", "probe_grid_set_distance",
+                 "probe_trace", "probe_trace_noalloc", "probe_trace_rays", "probe_grid_set_distance",
                  "probe_trace_backward", "probe_trace_backward_hits", "probe_trace_backward_distance",
                  "probe_autotune", "pt_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
@@ -298,6 +299,23 @@ def probe_trace(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None 
         _need(a, rays * k, what)
     _check(lib.probe_trace(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), _ptr(t), _ptr(st), _ptr(hit),
                            ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return dict(rgb=rgb, t=t, status=st, hit=hit)
+
+
+def probe_trace_noalloc(grid: ProbeGrid, radiance_half, views, out, opts: PtTraceOpts | None = None, stream=None):
+    """probe_trace through the entry point that allocates nothing (its scratch is a fixed
+    device array).  ``out`` = (rgb, t, status, hit) device tensors (t, status, hit may be
+    None), written in place and returned as a dict."""
+    lib = load_library()
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
+    rgb, t, st, hit = out
+    for a, k, what in ((rgb, 3, "rgb"), (t, 1, "t"), (st, 1, "status"), (hit, 2, "hit")):
+        _need(a, rays * k, what)
+    _check(lib.probe_trace_noalloc(grid.handle, _ptr(radiance_half), va, len(va), _ptr(rgb), _ptr(t), _ptr(st),
+                                   _ptr(hit), ctypes.byref(opts) if opts is not None else None, _stream(stream)))
     return dict(rgb=rgb, t=t, status=st, hit=hit)
 
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -44,6 +45,30 @@ static pt_status fail(pt_status s, const std::string &msg) {
     } while (0)
 
 extern "C" const char *pt_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------------------------
+// fixed scratch of probe_trace_noalloc: the cage-order tables of one view, both levels of
+// a hierarchy (fine cells first), in a device array every GPU the library runs on holds
+// until the process ends.  Host code never names the array in a launch or a copy: its
+// device address comes from hipGetSymbolAddress, once per device, while the grid is
+// created on that device.
+// ------------------------------------------------------------------------------------
+constexpr int kScratchWords = 1 << 18;  // 1 MiB: 262,144 cells of packed cage orders
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+constexpr int kMaxDevices = 64;
+static std::atomic<uint32_t *> g_scratch_dev[kMaxDevices];
+
+// Resolve this device's copy of `scratch`; `device` must be the current device.
+static pt_status resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(PT_ERR_UNSUPPORTED, "device index above 63");
+    if (g_scratch_dev[device].load(std::memory_order_acquire)) return PT_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(PT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[device].store((uint32_t *)p, std::memory_order_release);
+    return PT_OK;
+}
 
 // ------------------------------------------------------------------------------------
 // grid object
@@ -186,6 +211,10 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return fail(st, m);
     };
     if (hipGetDevice(&g->device) != hipSuccess) return cleanup(PT_ERR_HIP, "hipGetDevice failed");
+    {
+        pt_status ss = resolve_scratch(g->device);
+        if (ss != PT_OK) return cleanup(ss, g_err);
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g->num_cus = prop.multiProcessorCount;
     if (hipMalloc(&g->pyr, (size_t)(P * g->stride) * sizeof(float)) != hipSuccess)
@@ -778,6 +807,35 @@ static pt_status tile_shape(const pt_trace_opts *opts, int &tw, int &th) {
     return PT_OK;
 }
 
+// Check one view and fill its device record; rays and tiles are the running totals of the
+// views before it (advanced past this one).
+static pt_status view_to_dev(const pt_view &v, int tw, int th, int64_t &rays, int64_t &tiles, ViewDev &d) {
+    if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
+        return fail(PT_ERR_INVALID_ARGUMENT, "view size out of range");
+    if (!(v.tan_half_fov_y > 0.0f) || !std::isfinite(v.tan_half_fov_y))
+        return fail(PT_ERR_INVALID_ARGUMENT, "tan_half_fov_y must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(v.pos[a]) || !std::isfinite(v.right[a]) || !std::isfinite(v.up[a]) ||
+            !std::isfinite(v.fwd[a]))
+            return fail(PT_ERR_INVALID_ARGUMENT, "view position and axes must be finite");
+    for (int a = 0; a < 3; ++a) {
+        d.pos[a] = v.pos[a];
+        d.right[a] = v.right[a];
+        d.up[a] = v.up[a];
+        d.fwd[a] = v.fwd[a];
+    }
+    d.tanh = v.tan_half_fov_y;
+    d.W = v.width;
+    d.H = v.height;
+    d.ray_offset = rays;
+    d.tiles_x = (v.width + tw - 1) / tw;
+    d.tile_begin = (int)tiles;
+    tiles += (int64_t)d.tiles_x * ((v.height + th - 1) / th);
+    rays += (int64_t)v.width * v.height;
+    if (tiles > (int64_t)1 << 30) return fail(PT_ERR_INVALID_ARGUMENT, "too many tiles");
+    return PT_OK;
+}
+
 static pt_status check_views(const pt_view *views, int n_views, int tw, int th, std::vector<ViewDev> &vd,
                              int64_t &rays, int &tiles) {
     if (!views || n_views < 1) return fail(PT_ERR_INVALID_ARGUMENT, "need at least one view");
@@ -785,32 +843,9 @@ static pt_status check_views(const pt_view *views, int n_views, int tw, int th, 
     rays = 0;
     int64_t t = 0;
     for (int i = 0; i < n_views; ++i) {
-        const pt_view &v = views[i];
-        if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
-            return fail(PT_ERR_INVALID_ARGUMENT, "view size out of range");
-        if (!(v.tan_half_fov_y > 0.0f) || !std::isfinite(v.tan_half_fov_y))
-            return fail(PT_ERR_INVALID_ARGUMENT, "tan_half_fov_y must be finite and > 0");
-        for (int a = 0; a < 3; ++a)
-            if (!std::isfinite(v.pos[a]) || !std::isfinite(v.right[a]) || !std::isfinite(v.up[a]) ||
-                !std::isfinite(v.fwd[a]))
-                return fail(PT_ERR_INVALID_ARGUMENT, "view position and axes must be finite");
-        ViewDev &d = vd[i];
-        for (int a = 0; a < 3; ++a) {
-            d.pos[a] = v.pos[a];
-            d.right[a] = v.right[a];
-            d.up[a] = v.up[a];
-            d.fwd[a] = v.fwd[a];
-        }
-        d.tanh = v.tan_half_fov_y;
-        d.W = v.width;
-        d.H = v.height;
-        d.ray_offset = rays;
-        d.tiles_x = (v.width + tw - 1) / tw;
-        d.tile_begin = (int)t;
-        t += (int64_t)d.tiles_x * ((v.height + th - 1) / th);
-        rays += (int64_t)v.width * v.height;
+        pt_status st = view_to_dev(views[i], tw, th, rays, t, vd[i]);
+        if (st != PT_OK) return st;
     }
-    if (t > (int64_t)1 << 30) return fail(PT_ERR_INVALID_ARGUMENT, "too many tiles");
     tiles = (int)t;
     return PT_OK;
 }
@@ -939,6 +974,18 @@ static pt_status run_graph(pt_grid *g, const TraceCtx &c, const std::vector<View
     return PT_OK;
 }
 
+// One view's cage tables, then its trace: one wavefront per pixel tile, four per workgroup.
+static void launch_view(const pt_grid *g, const TraceCtx &c, const ViewDev &v, uint32_t *cage, uint32_t *ccage,
+                        const uint16_t *rad, const Outputs &o, int tw, int th, hipStream_t s) {
+    int vt = v.tiles_x * ((v.H + th - 1) / th);
+    unsigned nb = (unsigned)((vt + 3) / 4);
+    launch_cage_tables(g, c, nullptr, v, 1, cage, ccage, s);
+#define PT_LAUNCH(W, T) \
+    hipLaunchKernelGGL((k_trace_view<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, v, cage, ccage, rad, o, tw, th)
+    PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
+}
+
 static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_view *views, int n_views,
                             const Outputs &o, const pt_trace_opts *opts, hipStream_t s) {
     pt_grid *g = const_cast<pt_grid *>(cg);
@@ -966,17 +1013,9 @@ static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_vie
         if (st != PT_OK) return st;
         return launch_persistent(g, c, g->views_dev, g->cage, g->ccage, n_views, tiles, rad, o, tw, th, s);
     }
-    for (int i = 0; i < n_views; ++i) {
-        int vt = vd[i].tiles_x * ((vd[i].H + th - 1) / th);
-        unsigned nb = (unsigned)((vt + 3) / 4);
-        uint32_t *cage = g->cage + (int64_t)i * g->cells;
-        uint32_t *ccage = c.two ? g->ccage + (int64_t)i * c.ccells : nullptr;
-        launch_cage_tables(g, c, nullptr, vd[i], 1, cage, ccage, s);
-#define PT_LAUNCH(W, T) \
-    hipLaunchKernelGGL((k_trace_view<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], cage, ccage, rad, o, tw, th)
-        PT_DISPATCH(c, PT_LAUNCH);
-#undef PT_LAUNCH
-    }
+    for (int i = 0; i < n_views; ++i)
+        launch_view(g, c, vd[i], g->cage + (int64_t)i * g->cells, c.two ? g->ccage + (int64_t)i * c.ccells : nullptr,
+                    rad, o, tw, th, s);
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }
@@ -987,6 +1026,53 @@ extern "C" pt_status probe_trace(const pt_grid *g, const uint16_t *radiance_dev,
     if (!g || !radiance_dev || !rgb_dev) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace: NULL argument");
     Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
     return trace_impl(g, radiance_dev, views_host, n_views, o, opts, (hipStream_t)stream);
+}
+
+extern "C" pt_status probe_trace_noalloc(const pt_grid *g, const uint16_t *radiance_dev, const pt_view *views_host,
+                                         int32_t n_views, float *rgb_dev, float *t_dev, uint8_t *status_dev,
+                                         int32_t *hit_dev, const pt_trace_opts *opts, void *stream) {
+    if (!g || !radiance_dev || !rgb_dev || !views_host)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_noalloc: NULL argument");
+    if (n_views < 1) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_noalloc: need at least one view");
+    if (opts && (opts->flags & (PT_FLAG_PERSISTENT | PT_FLAG_GRAPH)))
+        return fail(PT_ERR_UNSUPPORTED,
+                    "probe_trace_noalloc: per-view launches only (persistent and graph launches use buffers the "
+                    "library allocates)");
+    int tw, th;
+    pt_status st = tile_shape(opts, tw, th);
+    if (st != PT_OK) return st;
+    TraceCtx c;
+    make_ctx(g, opts, c);
+    // one view's tables at a time: the launches of a stream run in order, so the next
+    // view's tables are written only after the previous view's trace has read its own
+    const int64_t fine_cells = std::max(1, g->cells);
+    const int64_t words = fine_cells + (c.two ? std::max(1, c.ccells) : 0);
+    if (words > kScratchWords)
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_noalloc: the grid has " + std::to_string(words) +
+                                                 " cells (both levels); the fixed scratch holds at most " +
+                                                 std::to_string(kScratchWords));
+    uint32_t *scr = g->device >= 0 && g->device < kMaxDevices
+                        ? g_scratch_dev[g->device].load(std::memory_order_acquire)
+                        : nullptr;
+    if (!scr) return fail(PT_ERR_HIP, "probe_trace_noalloc: scratch address of the grid's device not resolved");
+    // every view is checked before anything is enqueued
+    int64_t rays = 0, tiles = 0;
+    for (int i = 0; i < n_views; ++i) {
+        ViewDev d;
+        st = view_to_dev(views_host[i], tw, th, rays, tiles, d);
+        if (st != PT_OK) return st;
+    }
+    Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
+    rays = 0;
+    tiles = 0;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n_views; ++i) {
+        ViewDev d;
+        (void)view_to_dev(views_host[i], tw, th, rays, tiles, d);
+        launch_view(g, c, d, scr, c.two ? scr + fine_cells : nullptr, radiance_dev, o, tw, th, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
 }
 
 extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance_dev, const float *origins_dev,

@@ -62,6 +62,8 @@ def test_host_side_argument_errors():
     assert lib.probe_trace(None, None, None, 0, None, None, None, None, None, None) == 1
     assert lib.probe_trace_backward(None, None, 0, None, None, None, None) == 1
     assert lib.probe_trace_rays(None, None, None, None, 0, None, None, None, None, None, None) == 1
+    assert lib.probe_trace_noalloc(None, None, None, 0, None, None, None, None, None, None) == 1
+    assert b"NULL" in lib.pt_last_error()
     o = pt.PtTraceOpts()
     lib.pt_trace_opts_default(ctypes.byref(o))
     assert o.max_probes_per_cell == 8 and o.tile_w * o.tile_h == 64 and o.start_level == -1
