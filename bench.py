@@ -7,13 +7,15 @@ view.  value = rays traced per second (Mrays/s), inputs resident in HBM.
 
 Also reported: forward+backward Mrays/s on the same view (trace + radiance adjoint),
 the batched workload (64 views of uneven size in one persistent hipGraph launch) against
-64 plain launches, the roofline of the forward kernel and the CPU oracle timed on the
-host.
+64 plain launches, the differentiable grid's training step kernel by kernel, the
+two-level city block (8 views of 3840x2160), the HBM roofline of each workload's kernels
+(algorithmic bytes from tests/golden/algorithmic_bytes.json over the measured launch
+time, against 8 TB/s) and the CPU oracle timed on the host.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--autotune]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--autotune] [--legs LIST]
 
 Launch options (tile shape, pyramid start level, launch form) come from the autotuner's
-stored choice for this workload (paper_2507_14624_amd/tuned.json); --autotune re-tunes.
+stored choice for each workload (paper_2507_14624_amd/tuned.json); --autotune re-tunes.
 """
 import argparse
 import hashlib
@@ -65,6 +67,19 @@ def measured_valu():
     if not v or not w or not s or s.group(1) != kernel_source_hash():
         return None
     return float(v.group(1)), int(w.group(1))
+
+
+def hbm_roof(total_bytes, ms, kernel):
+    """Algorithmic bytes of one launch over its measured duration, against HBM peak."""
+    gbs = total_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "kernel": kernel, "algorithmic_bytes_per_launch": int(total_bytes),
+            "ms": round(ms, 4)}
+
+
+def algorithmic():
+    with open(BYTES_FILE) as fh:
+        return json.load(fh)
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -198,6 +213,34 @@ def differentiable(pt, synth, torch, np, steps=5):
     e1.record()
     torch.cuda.synchronize()
     ms_fh = e0.elapsed_time(e1) / steps
+
+    def alone(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # each kernel of the step on its own, against its algorithmic bytes
+    ab = algorithmic().get("diff_32x512")
+    ms_k = {"forward": alone(lambda: pt.probe_trace(grid, storage, va, po, out=hout)),
+            "adjoint_stored_hits": alone(lambda: pt.probe_trace_backward_hits(grid, va, hout[3], hout[1], gr, g, po)),
+            "adjoint_recompute": alone(lambda: pt.probe_trace_backward(grid, va, gr, g, po))}
+    m1, m2 = torch.zeros_like(fit.master), torch.zeros_like(fit.master)
+    pm = fit.master.detach().clone()
+    ms_k["adam"] = alone(lambda: pt.adam_step(pm, g.view(pm.shape), m1, m2, storage, 1, 1e-2))
+    del m1, m2, pm
+    kernels = {}
+    if ab is not None:
+        kernels = {"forward": hbm_roof(ab["total_bytes"], ms_k["forward"], "k_trace_persistent<false, 0>"),
+                   "adjoint_stored_hits": hbm_roof(ab["adjoint_stored_hits_total_bytes"], ms_k["adjoint_stored_hits"],
+                                                   "k_backward_hits<0>"),
+                   "adjoint_recompute": hbm_roof(ab["adjoint_recompute_total_bytes"], ms_k["adjoint_recompute"],
+                                                 "k_backward_persistent<false, 0, false>"),
+                   "adam": hbm_roof(ab["adam_total_bytes"], ms_k["adam"], "k_adam_fp16")}
     del hout
     # gradient through the stored distances: forward (rgb and t) + distance adjoint
     del g
@@ -226,6 +269,7 @@ def differentiable(pt, synth, torch, np, steps=5):
                           "loss": [round(x, 6) for x in losses],
                           "adjoint": "recomputes the trace"},
             "launch": "one persistent launch over the 32 views, forward and adjoint",
+            "kernels_roofline": kernels,
             "geometry_fwd_bwd_kernels_ms": round(ms_geo, 3),
             "geometry_fwd_bwd_mrays_s": round(rays / (ms_geo * 1e-3) / 1e6, 2),
             "loss": [round(x, 6) for x in losses_sh]}
@@ -328,6 +372,11 @@ def large(pt, synth, torch, np, steps=3):
     torch.cuda.synchronize()
     ms_fh = e0.elapsed_time(e1) / steps
     del hout
+    ab = algorithmic().get("large_8x4k")
+    roof = {}
+    if ab is not None:
+        roof = {"forward": hbm_roof(ab["total_bytes"], ms, "k_trace_persistent<true, 1>"),
+                "bytes_per_ray": round(ab["bytes_per_ray"], 2), "sample": ab.get("sample")}
     return {"workload": f"city block of {n_boxes} boxes; fine 64x64x16 + coarse 16x16x4 probes (coarse planes = every "
                         f"4th fine plane), 128^2 maps, 5-level pyramids, {P} probes ({dead:.0%} inside buildings, "
                         f"D = 0); 8 views of 3840x2160", "rays": rays, "hbm_probe_bytes": int(P * N * N * (8 + 4 + 6)),
@@ -336,7 +385,11 @@ def large(pt, synth, torch, np, steps=3):
                     "launch": "one graph-captured persistent launch over the 8 views"},
             "fwd_bwd": {"value": round(rays / (ms_fb * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms": round(ms_fb, 3)},
             "fwd_bwd_stored_hits": {"value": round(rays / (ms_fh * 1e-3) / 1e6, 2), "unit": "Mrays/s",
-                                    "ms": round(ms_fh, 3)}}
+                                    "ms": round(ms_fh, 3)},
+            "roofline": roof}
+
+
+LEGS = ("fwd_bwd", "batched", "diff", "bake", "paper", "large", "cpu")
 
 
 def main():
@@ -344,11 +397,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="forward only (for profiling)")
-    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable workload")
-    ap.add_argument("--large", action="store_true",
-                    help="also the two-level city block (bakes ~17 GB of probes on the host first)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="workloads besides the single-view forward: " + ",".join(LEGS) + " (or none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="leave out the leg 'cpu'")
+    ap.add_argument("--no-large", action="store_true",
+                    help="leave out the leg 'large' (it bakes ~20 GB of probes on the host first)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the tuned options")
     ap.add_argument("--autotune", action="store_true", help="re-run the autotuner and store its choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -368,6 +421,15 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (rays would shard by "
               "view, with the probe set replicated on every GPU).", file=sys.stderr)
         sys.exit(2)
+    legs = set() if args.legs in ("", "none") else set(args.legs.split(","))
+    unknown = legs - set(LEGS)
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if args.no_cpu_baseline:
+        legs.discard("cpu")
+    if args.no_large:
+        legs.discard("large")
 
     import numpy as np
     import torch
@@ -396,12 +458,24 @@ def main():
     ms, wall = time_steps(fwd, args.steps, args.warmup, torch)
     value = rays / (ms * 1e-3) / 1e6
 
-    with open(BYTES_FILE) as fh:
-        ab = json.load(fh)["single_1080p"]
-    achieved_gbs = ab["total_bytes"] / (ms * 1e-3) / 1e9
+    allab = algorithmic()
+    ab = allab["single_1080p"]
     achieved_tflops = ab["total_flops"] / (ms * 1e-3) / 1e12
-    traffic = measured_traffic()
     kernel = "k_trace_persistent<false, 0>" if opts.flags & pt.PT_FLAG_PERSISTENT else "k_trace_view<false, 0>"
+    # The HBM roof: algorithmic bytes of one frame (the oracle's count on the reference
+    # schedule) over the step's duration, which the HIP events around the steps measure on
+    # the stream the library launches on (one k_cage_order and one trace launch per step).
+    roof = hbm_roof(ab["total_bytes"], ms, kernel)
+    roof["traffic"] = measured_traffic()
+    roof["bytes_per_ray"] = round(ab["bytes_per_ray"], 2)
+    roof["target_frac"] = 0.5
+    roof["target_met"] = roof["frac"] >= 0.5
+    # What bounds it in fact: vector-ALU issue (rocprofv3 SQ counters); the probe set is
+    # cache resident.  FP32 peak without packed-FP32 instructions: 256 CUs x 64 lanes x 2
+    # flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+    roof["alu"] = {"achieved": round(achieved_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 5),
+                   "algorithmic_flops_per_launch": ab["total_flops"], "flops_per_ray": round(ab["flops_per_ray"], 1)}
     result = {
         "metric": "Mrays/s probe trace (fwd, fwd+bwd) at 1080p; HBM GB/s vs peak; batched vs plain",
         "value": round(value, 3),
@@ -419,17 +493,7 @@ def main():
                                "128x128 octahedral maps (FP32 distance, FP16 normal/radiance), 5-level min pyramid",
                    "rays_per_step": rays, "tile": [opts.tile_w, opts.tile_h], "start_level": opts.start_level,
                    "launch": "persistent" if opts.flags & pt.PT_FLAG_PERSISTENT else "per-view"},
-        # The trace is bound by vector-ALU issue (rocprofv3 SQ counters), not by HBM: the
-        # probe set is cache resident.  FP32 peak without packed-FP32 instructions:
-        # 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 5), "traffic": traffic,
-                     "kernel": kernel, "algorithmic_flops_per_launch": ab["total_flops"],
-                     "flops_per_ray": round(ab["flops_per_ray"], 1),
-                     "hbm": {"achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(achieved_gbs / HBM_PEAK_GBS, 5),
-                             "algorithmic_bytes_per_launch": ab["total_bytes"],
-                             "bytes_per_ray": round(ab["bytes_per_ray"], 2)}},
+        "roofline": roof,
     }
     valu = measured_valu()
     tiles = -(-view.width // opts.tile_w) * -(-view.height // opts.tile_h)  # one wavefront per tile
@@ -440,7 +504,7 @@ def main():
         result["roofline"]["valu_issue"] = {"instructions_per_launch": int(valu[0] * valu[1]),
                                             "issue_ms": round(issue_ms, 4), "frac": round(issue_ms / ms, 4),
                                             "source": "rocprofv3 SQ_INSTS_VALU (profiles/)"}
-    if not args.no_extras:
+    if "fwd_bwd" in legs:
         gsz = (probes.n_probes, probes.N, probes.N, 3)
         grad = torch.zeros(gsz, device="cuda")
         gout = torch.randn((rays, 3), device="cuda")
@@ -465,34 +529,48 @@ def main():
         ms_fh, _ = time_steps(fwd_bwd_hits, max(3, args.steps // 2), 1, torch)
         result["fwd_bwd_stored_hits"] = {"value": round(rays / (ms_fh * 1e-3) / 1e6, 3), "unit": "Mrays/s",
                                          "ms_per_step": round(ms_fh, 4),
-                                         "adjoint": "from the forward's hit and t outputs (12 B/ray kept: probe and texel as int32, t as FP32)"}
+                                         "adjoint": "from the forward's hit and t outputs (12 B/ray kept: probe and "
+                                                    "texel as int32, t as FP32)"}
+        ms_a, _ = time_steps(lambda: pt.probe_trace_backward_hits(grid, va, hout[3], hout[1], gout, grad, opts),
+                             max(3, args.steps // 2), 1, torch)
+        result["fwd_bwd_stored_hits"]["adjoint_roofline"] = hbm_roof(ab["adjoint_stored_hits_total_bytes"], ms_a,
+                                                                     "k_backward_hits<0>")
+    if "batched" in legs:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         _, _, bviews = synth.workload("batched")
         bva = pt.make_views(bviews)
         brays = pt.n_rays(bviews)
         bout = (torch.empty((brays, 3), device="cuda"), None, None, None)
-        gopts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level,
-                              flags=pt.PT_FLAG_GRAPH)
-        popts = pt.trace_opts(tile=(opts.tile_w, opts.tile_h), start_level=opts.start_level)  # one launch per view
+        # the 64-view launch tuned on its own views, starting from the graph launch form
+        gopts = pt.trace_opts() if args.no_autotune else tuning.options(
+            "batched_64", grid, rad, bva, retune=args.autotune, flags=pt.PT_FLAG_GRAPH)
+        gopts.flags |= pt.PT_FLAG_GRAPH
+        popts = pt.trace_opts(tile=(gopts.tile_w, gopts.tile_h), start_level=gopts.start_level)  # per view
         ms_g, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, gopts, out=bout), 3, 1, torch)
         ms_p, _ = time_steps(lambda: pt.probe_trace(grid, rad, bva, popts, out=bout), 3, 1, torch)
+        bab = allab.get("batched_64")
         result["batched"] = {"views": len(bviews), "rays": brays,
+                             "options": {"tile": [gopts.tile_w, gopts.tile_h], "start_level": gopts.start_level,
+                                         "flags": int(gopts.flags)},
                              "graph_persistent": {"value": round(brays / (ms_g * 1e-3) / 1e6, 3), "unit": "Mrays/s",
                                                   "ms": round(ms_g, 3)},
                              "plain_launches": {"value": round(brays / (ms_p * 1e-3) / 1e6, 3), "unit": "Mrays/s",
-                                                "ms": round(ms_p, 3)}}
-    if not args.no_extras and not args.no_diff:
+                                                "ms": round(ms_p, 3)},
+                             "roofline": hbm_roof(bab["total_bytes"], ms_g, "k_trace_persistent<false, 0>")
+                             if bab else None}
+    if "diff" in legs:
         print("[bench] differentiable workload", file=sys.stderr, flush=True)
         result["differentiable"] = differentiable(pt, synth, torch, np)
-    if not args.no_extras:
+    if "bake" in legs:
         print("[bench] point-cloud bake", file=sys.stderr, flush=True)
         result["bake"] = bake(pt, synth, torch, np)
+    if "paper" in legs:
         print("[bench] paper map configuration", file=sys.stderr, flush=True)
         result["paper_maps"] = paper_maps(pt, synth, torch, np)
-    if args.large:
+    if "large" in legs:
         print("[bench] large two-level workload", file=sys.stderr, flush=True)
         result["large"] = large(pt, synth, torch, np)
-    if not args.no_cpu_baseline:
+    if "cpu" in legs:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(probes, view)
         cb["one_thread"]["value"] = round(cb["one_thread"]["value"], 4)  # other_workloads are rounded already

@@ -288,7 +288,10 @@ pt_status probe_grid_set_distance(pt_grid *grid, const float *distance_dev, void
 /* Choose tile shape, pyramid start level and launch form (per-view launches or one
  * persistent launch; PT_FLAG_GRAPH is kept if the caller set it) for these views by timing
  * candidate launches on `stream` (synchronous; writes into rgb_dev, which must hold the
- * views' rays).  Results do not depend on the choice.  *opts is read for the algorithm
+ * views' rays).  A sweep of every candidate, then the three fastest and the default (8x8
+ * tiles from the coarsest level, the caller's launch form) timed again in 5 interleaved
+ * rounds; a candidate replaces the default only if its median round is more than 1%
+ * faster.  Results do not depend on the choice.  *opts is read for the algorithm
  * constants and receives tile_w, tile_h, start_level and flags.  Errors: INVALID_ARGUMENT,
  * HIP. */
 pt_status probe_autotune(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,

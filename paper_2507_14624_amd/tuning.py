@@ -47,12 +47,13 @@ def apply(opts, entry: dict):
     return opts
 
 
-def options(key: str, grid, radiance_half, views, retune: bool = False):
-    """Stored options for `key`, tuning (and storing) them first if absent or asked."""
+def options(key: str, grid, radiance_half, views, retune: bool = False, flags: int = 0):
+    """Stored options for `key`, tuning (and storing) them first if absent or asked.
+    `flags` is the launch form the tuner starts from (PT_FLAG_GRAPH is kept)."""
     from . import probe_autotune, trace_opts
     entry = None if retune else load(key)
     if entry is not None:
         return apply(trace_opts(), entry)
-    opts = probe_autotune(grid, radiance_half, views, trace_opts())
-    save(key, opts, note="probe_autotune on MI355X")
+    opts = probe_autotune(grid, radiance_half, views, trace_opts(flags=flags))
+    save(key, opts, note=f"probe_autotune on MI355X over {len(views)} view(s)")
     return opts
