@@ -122,6 +122,13 @@ typedef struct {
                                       piece pays for itself; off above, where it is an HBM
                                       access per piece.  This flag forces it on ... */
 #define PT_FLAG_NO_START_TEXEL 32u /* ... and this one off (it wins if both are set) */
+#define PT_FLAG_FP64 64u  /* probe_trace / probe_trace_rays: the whole trace in double precision
+                             (rays from the FP32 inputs widened to double, cages sorted per
+                             ray, outputs rounded to FP32), one launch per view: decisions
+                             FP32 cannot resolve (a gap near 1e-8 relative, as the finer
+                             2048^2 maps meet every few thousand rays) are taken as the
+                             double-precision definition takes them.  Several times slower;
+                             the adjoints ignore it */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 
@@ -277,6 +284,44 @@ pt_status probe_trace_backward_hits(const pt_grid *grid, const pt_view *views_ho
 pt_status probe_trace_backward_distance(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
                                         int32_t n_views, const float *grad_rgb_dev, const float *grad_t_dev,
                                         float *grad_distance_dev, const pt_trace_opts *opts, void *stream);
+
+/* Soft visibility: a relaxation of the HIT/UNKNOWN decision (Methodology, Ray Tracing Using
+ * One Probe; appendix highResolutionTracing) that lets gradients move it; an extension, the
+ * paper's classification is hard.  Every probe trace, in the walk order of probe_trace,
+ * whose first firing texel faces the ray (stored normal . w < 0) is a candidate j, accepted
+ * with weight
+ *     a_j = logistic(x_j),  x_j = (r_j (1 + tau) - rho_in,j) / (sigma r_j)   (0 if r_j <= 0)
+ * (r_j the texel's stored distance, rho_in,j the ray's distance from the probe where it
+ * enters the texel, tau = opts->thickness_rel); the colour is
+ *     rgb = sum_j a_j prod_{i<j} (1 - a_i) c_j + prod_j (1 - a_j) background,
+ * c_j the bilinear radiance at candidate j's hit point (as probe_trace's: the texel's entry
+ * point if entered at or behind the stored distance, else where rho = r; nearest texel with
+ * PT_FLAG_NEAREST).  The walk ends once prod (1 - a) <= 1e-6.  The march and the fire tests
+ * are probe_trace's, and sigma -> 0 gives probe_trace's colour.
+ *   sigma    > 0, finite: temperature relative to the stored distance
+ *   rgb_dev  [rays][3] FP32 out
+ * One persistent launch over the tiles of all views.  Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace_soft(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
+                           int32_t n_views, float sigma, float *rgb_dev, const pt_trace_opts *opts, void *stream);
+
+/* Adjoint of probe_trace_soft, the candidates and the fire tests held: with w_j =
+ * a_j prod_{i<j} (1 - a_i), A_j = sum_{k<=j} w_k c_k and g = grad_rgb of the ray,
+ *     dL/dx_j = g . (w_j (1 - a_j) c_j - a_j (rgb - A_j)),
+ *     grad_distance[candidate j's texel] += dL/dx_j rho_in,j / (sigma r_j^2)
+ *                                            + w_j (g . dc_j/dt) dt_j/dr_j,
+ *     grad_radiance[candidate j's taps]   += w_j * bilinear weight * g
+ * (dt/dr and dc/dt as in probe_trace_backward_distance; a term with an infinite dt/dr, at an
+ * exact tangency, is left out).
+ *   rgb_dev            [rays][3] FP32: probe_trace_soft's output for the same inputs
+ *   grad_rgb_dev       [rays][3] FP32
+ *   grad_distance_dev  [P][N][N] FP32, ACCUMULATED (+=), or NULL
+ *   grad_radiance_dev  [P][N][N][3] FP32, ACCUMULATED (+=), or NULL (not both NULL)
+ * In a two-level hierarchy P counts both levels, fine first.  FP32 atomics per candidate
+ * (summation order depends on scheduling).  Errors: INVALID_ARGUMENT, HIP. */
+pt_status probe_trace_soft_backward(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
+                                    int32_t n_views, float sigma, const float *rgb_dev, const float *grad_rgb_dev,
+                                    float *grad_distance_dev, float *grad_radiance_dev, const pt_trace_opts *opts,
+                                    void *stream);
 
 /* Replace the distance maps of a grid (level 0 of every probe) from distance_dev
  * ([P][N][N] FP32, this grid's probes only) and rebuild its MIN pyramid, on `stream`; the

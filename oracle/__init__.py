@@ -370,7 +370,8 @@ def vjp_soft(grid, result: dict, grad_rgb: np.ndarray):
         rin = result["rin"][on, j]
         dxdr = np.where(rk > 0.0, rin / (sigma * np.where(rk > 0.0, rk, 1.0) ** 2), 0.0)
         geo = wj * np.einsum("ij,ij->i", g[on], result["drgbdt"][on, j]) * result["dtdr"][on, j]
-        geo = np.where(wj != 0.0, geo, 0.0)  # dt/dr may be infinite at tangency, where w_j = 0
+        # dt/dr is infinite at an exact tangency: such a term is left out
+        geo = np.where((wj != 0.0) & np.isfinite(geo), geo, 0.0)
         flat = result["probe"][on, j].astype(np.int64) * (N * N) + result["texel"][on, j]
         np.add.at(gd, flat, dx * dxdr + geo)
         taps = result["probe"][on, j].astype(np.int64)[:, None] * (N * N) + result["taps"][on, j]

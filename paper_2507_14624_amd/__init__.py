@@ -25,11 +25,13 @@ PT_FLAG_NEAREST = 4
 PT_FLAG_WIDE = 8
 PT_FLAG_START_TEXEL = 16
 PT_FLAG_NO_START_TEXEL = 32
+PT_FLAG_FP64 = 64
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",
             "probe_trace", "probe_trace_noalloc", "probe_trace_rays", "probe_trace_backward", "probe_trace_backward_hits",
-            "probe_trace_backward_distance", "probe_autotune", "pt_adam_step", "pt_last_error")
+            "probe_trace_backward_distance", "probe_trace_soft", "probe_trace_soft_backward", "probe_autotune",
+            "pt_adam_step", "pt_last_error")
 
 
 class PtGridDesc(ctypes.Structure):
@@ -83,6 +85,10 @@ def load_library(path: str = LIB_PATH):
     lib.probe_trace_backward_distance.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, vp, vp, vp,
                                                   ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_grid_set_distance.argtypes = [vp, vp, vp]
+    lib.probe_trace_soft.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, ctypes.c_float, vp,
+                                     ctypes.POINTER(PtTraceOpts), vp]
+    lib.probe_trace_soft_backward.argtypes = [vp, vp, ctypes.POINTER(PtView), i32, ctypes.c_float, vp, vp, vp, vp,
+                                              ctypes.POINTER(PtTraceOpts), vp]
     lib.probe_trace_backward_hits.argtypes = [vp, ctypes.POINTER(PtView), i32, vp, vp, vp, vp,
                                               ctypes.POINTER(PtTraceOpts), vp]
     f64 = ctypes.c_double
@@ -90,7 +96,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("probe_grid_create", "probe_grid_read_level", "probe_grid_set_coarse", "probe_bake_points",
                  "probe_trace", "probe_trace_noalloc", "probe_trace_rays", "probe_grid_set_distance",
                  "probe_trace_backward", "probe_trace_backward_hits", "probe_trace_backward_distance",
-                 "probe_autotune", "pt_adam_step"):
+                 "probe_trace_soft", "probe_trace_soft_backward", "probe_autotune", "pt_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
     lib.pt_last_error.argtypes = []
     lib.pt_last_error.restype = ctypes.c_char_p
@@ -395,6 +401,50 @@ def probe_trace_backward_distance(grid: ProbeGrid, radiance_half, views, grad_rg
     return grad_distance
 
 
+def probe_trace_soft(grid: ProbeGrid, radiance_half, views, sigma: float, opts: PtTraceOpts | None = None,
+                     out=None, stream=None):
+    """Soft-visibility colour [rays,3] (probe_trace_soft): the candidates of the walk mixed
+    by logistic acceptance weights of temperature sigma (relative to the stored distance)."""
+    lib = load_library()
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    _need(radiance_half, grid.P_total * grid.N * grid.N * 3, "radiance")
+    rgb = out if out is not None else torch.empty((rays, 3), dtype=torch.float32, device=radiance_half.device)
+    _need(rgb, 3 * rays, "rgb")
+    _check(lib.probe_trace_soft(grid.handle, _ptr(radiance_half), va, len(va), float(sigma), _ptr(rgb),
+                                ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return rgb
+
+
+def probe_trace_soft_backward(grid: ProbeGrid, radiance_half, views, sigma: float, rgb, grad_rgb,
+                              grad_distance=None, grad_radiance=None, opts: PtTraceOpts | None = None, stream=None):
+    """Adjoint of probe_trace_soft: accumulates (+=) into grad_distance [P_total,N,N] and/or
+    grad_radiance [P_total,N,N,3] (FP32); rgb is the forward's output."""
+    lib = load_library()
+    radiance_half = _dev_tensor(radiance_half, torch.float16, "radiance (FP16)")
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    rays = sum(v.width * v.height for v in va)
+    P, N = grid.P_total, grid.N
+    _need(radiance_half, P * N * N * 3, "radiance")
+    rgb = _dev_tensor(rgb, torch.float32, "rgb")
+    grad_rgb = _dev_tensor(grad_rgb, torch.float32, "grad_rgb")
+    _need(rgb, 3 * rays, "rgb")
+    _need(grad_rgb, 3 * rays, "grad_rgb")
+    if grad_distance is None and grad_radiance is None:
+        raise ProbeTraceError("probe_trace_soft_backward: no gradient requested")
+    if grad_distance is not None:
+        grad_distance = _dev_tensor(grad_distance, torch.float32, "grad_distance")
+        _need(grad_distance, P * N * N, "grad_distance")
+    if grad_radiance is not None:
+        grad_radiance = _dev_tensor(grad_radiance, torch.float32, "grad_radiance")
+        _need(grad_radiance, P * N * N * 3, "grad_radiance")
+    _check(lib.probe_trace_soft_backward(grid.handle, _ptr(radiance_half), va, len(va), float(sigma), _ptr(rgb),
+                                         _ptr(grad_rgb), _ptr(grad_distance), _ptr(grad_radiance),
+                                         ctypes.byref(opts) if opts is not None else None, _stream(stream)))
+    return grad_distance, grad_radiance
+
+
 def probe_autotune(grid: ProbeGrid, radiance_half, views, opts: PtTraceOpts | None = None, stream=None):
     """Time candidate tile shapes and start levels; returns the tuned options."""
     lib = load_library()
@@ -497,3 +547,38 @@ class ProbeGeometryFn(torch.autograd.Function):
             gm = torch.zeros(ctx.mshape, dtype=torch.float32, device=dev)
             probe_trace_backward(ctx.grid, ctx.views, grad_rgb, gm, ctx.opts)
         return gd, gm, None, None, None
+
+
+class ProbeSoftFn(torch.autograd.Function):
+    """rgb = soft-visibility trace(distance, radiance) of a single-level grid
+    (probe_trace_soft), with gradients for the stored distances that move the HIT/UNKNOWN
+    decision and for the radiance (probe_trace_soft_backward).
+
+    forward: the grid's distance maps are replaced by `distance` ([P,N,N] FP32; the MIN
+    pyramid is rebuilt) and the FP32 master radiance is rounded to FP16 storage;
+    backward: the candidates and the fire tests held, the FP16 rounding passed straight
+    through to the master."""
+
+    @staticmethod
+    def forward(ctx, distance, master, grid, views, sigma, opts=None):
+        if grid.P_total != grid.P:
+            raise ProbeTraceError("ProbeSoftFn: single-level grids only")
+        grid.set_distance(distance.detach().contiguous())
+        storage = master.detach().to(torch.float16).contiguous()
+        va = views if isinstance(views, ctypes.Array) else make_views(views)
+        rgb = probe_trace_soft(grid, storage, va, sigma, opts)
+        ctx.grid, ctx.views, ctx.opts, ctx.storage, ctx.sigma = grid, va, opts, storage, float(sigma)
+        ctx.dshape, ctx.mshape = distance.shape, master.shape
+        ctx.save_for_backward(rgb)
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        (rgb,) = ctx.saved_tensors
+        dev = ctx.storage.device
+        gd = torch.zeros(ctx.dshape, dtype=torch.float32, device=dev) if ctx.needs_input_grad[0] else None
+        gm = torch.zeros(ctx.mshape, dtype=torch.float32, device=dev) if ctx.needs_input_grad[1] else None
+        if gd is not None or gm is not None:
+            probe_trace_soft_backward(ctx.grid, ctx.storage, ctx.views, ctx.sigma, rgb, grad_rgb.contiguous().float(),
+                                      gd, gm, ctx.opts)
+        return gd, gm, None, None, None, None

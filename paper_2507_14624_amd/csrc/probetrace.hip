@@ -311,7 +311,7 @@ struct Outputs {
     int32_t *hit;
 };
 
-__device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult &r,
+__device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *__restrict__ rad, const RayResult<float> &r,
                                              int64_t ray, const Outputs &o) {
     float rgb[3] = {g.bg[0], g.bg[1], g.bg[2]};
     if (r.status == ST_HIT) {
@@ -363,7 +363,7 @@ PT_TRACE_KERNEL k_trace_view(GridDev g, Level2 L2, ViewDev v, const uint32_t *__
     if (x >= v.W || y >= v.H) return;
     float w[3];
     camera_ray(v, x, y, w);
-    RayResult r;
+    RayResult<float> r;
     trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
     write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
 }
@@ -376,7 +376,7 @@ PT_TRACE_KERNEL k_trace_rays(GridDev g, Level2 L2, const float *__restrict__ ori
     float X[3] = {orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
     float d[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
     float l2 = __fmaf_rn(d[2], d[2], __fmaf_rn(d[1], d[1], d[0] * d[0]));
-    RayResult r;
+    RayResult<float> r;
     if (!(l2 > 0.0f) || !isfinite(l2)) {
         r.status = ST_MISS;
         r.probe = -1;
@@ -388,6 +388,69 @@ PT_TRACE_KERNEL k_trace_rays(GridDev g, Level2 L2, const float *__restrict__ ori
         trace_ray<W, T>(g, L2, X, w, nullptr, nullptr, r);
     }
     write_result(g, rad, r, i, o);
+}
+
+// The exact re-trace (PT_FLAG_FP64): the same trace in double precision.  Rays come from
+// the FP32 view parameters (or FP32 origins and directions) widened to double, every lane
+// sorts its own cages in double, and the outputs are rounded to FP32 at the end.
+__device__ __forceinline__ void write_result64(const GridDev &g, const uint16_t *__restrict__ rad,
+                                               const RayResult<double> &r, int64_t ray, const Outputs &o) {
+    double rgb[3] = {g.bg[0], g.bg[1], g.bg[2]};
+    if (r.status == ST_HIT) {
+        int idx[4];
+        double wt[4];
+        hit_radiance(g, rad, r, rgb, idx, wt);
+    }
+    o.rgb[3 * ray + 0] = (float)rgb[0];
+    o.rgb[3 * ray + 1] = (float)rgb[1];
+    o.rgb[3 * ray + 2] = (float)rgb[2];
+    if (o.t) o.t[ray] = r.status == ST_HIT ? (float)r.t : INFINITY;
+    if (o.status) o.status[ray] = (uint8_t)r.status;
+    if (o.hit) {
+        o.hit[2 * ray + 0] = r.status == ST_HIT ? r.probe : -1;
+        o.hit[2 * ray + 1] = r.status == ST_HIT ? r.texel : -1;
+    }
+}
+
+template <bool W, int T>
+__global__ void __launch_bounds__(256) k_trace_view_fp64(GridDev g, Level2 L2, ViewDev v,
+                                                         const uint16_t *__restrict__ rad, Outputs o, int tw, int th) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int tile = blockIdx.x * 4 + wave;
+    int tiles_y = (v.H + th - 1) / th;
+    if (tile >= v.tiles_x * tiles_y) return;
+    int x = (tile % v.tiles_x) * tw + lane % tw;
+    int y = (tile / v.tiles_x) * th + lane / tw;
+    if (x >= v.W || y >= v.H) return;
+    double w[3];
+    camera_ray(v, x, y, w);
+    const double X[3] = {v.pos[0], v.pos[1], v.pos[2]};
+    RayResult<double> r;
+    trace_ray<W, T>(g, L2, X, w, nullptr, nullptr, r);
+    write_result64(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
+}
+
+template <bool W, int T>
+__global__ void __launch_bounds__(256) k_trace_rays_fp64(GridDev g, Level2 L2, const float *__restrict__ orig,
+                                                         const float *__restrict__ dirs, int64_t n,
+                                                         const uint16_t *__restrict__ rad, Outputs o) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double X[3] = {orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
+    const double d[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+    const double l2 = __fma_rn(d[2], d[2], __fma_rn(d[1], d[1], d[0] * d[0]));
+    RayResult<double> r;
+    if (!(l2 > 0.0) || !isfinite(l2)) {
+        r.status = ST_MISS;
+        r.probe = -1;
+        r.texel = -1;
+        r.t = INFINITY;
+    } else {
+        const double inv = 1.0 / sqrt(l2);
+        const double w[3] = {d[0] * inv, d[1] * inv, d[2] * inv};
+        trace_ray<W, T>(g, L2, X, w, nullptr, nullptr, r);
+    }
+    write_result64(g, rad, r, i, o);
 }
 
 // Persistent multi-view trace: every wavefront pops tiles from a device counter until the
@@ -419,7 +482,7 @@ PT_TRACE_KERNEL k_trace_persistent(GridDev g, Level2 L2, const ViewDev *__restri
         if (x < v.W && y < v.H) {
             float w[3];
             camera_ray(v, x, y, w);
-            RayResult r;
+            RayResult<float> r;
             trace_ray<W, T>(g, L2, v.pos, w, cage + (int64_t)lo * cells, T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr,
                             r);
             write_result(g, rad, r, v.ray_offset + (int64_t)y * v.W + x, o);
@@ -538,7 +601,7 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
         if (x < v.W && y < v.H) {
             float w[3];
             camera_ray(v, x, y, w);
-            RayResult r;
+            RayResult<float> r;
             trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
             if (r.status == ST_HIT && r.dtdr != 0.0f) {
                 int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
@@ -563,7 +626,7 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
     if (x < v.W && y < v.H) {
         float w[3];
         camera_ray(v, x, y, w);
-        RayResult r;
+        RayResult<float> r;
         trace_ray<W, T>(g, L2, v.pos, w, cage, ccage, r);
         if (r.status == ST_HIT) {
             int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
@@ -647,7 +710,7 @@ __global__ void __launch_bounds__(256) k_backward_hits(GridDev g, Level2 L2, con
         float Xp[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) Xp[a] = v.pos[a] - grid_coord(G, a, pc[a]);
-        RayResult r;
+        RayResult<float> r;
         r.status = ST_HIT;
         r.probe = p;
         r.texel = texel;
@@ -692,6 +755,55 @@ PT_TRACE_KERNEL k_backward_persistent(GridDev g, Level2 L2, const ViewDev *__res
         }
         backward_tile<W, T, Geo>(g, L2, views[lo], tile - views[lo].tile_begin, cage + (int64_t)lo * cells,
                                  T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr, io, tw, th);
+    }
+}
+
+// Soft visibility (the visitors SoftFwd / SoftBwd of trace_device.h): the soft forward
+// (Bwd = false) or its adjoint over the tiles of all views, popped from a device counter
+// by whole wavefronts.
+template <bool W, int T, bool Bwd>
+PT_TRACE_KERNEL k_soft_persistent(GridDev g, Level2 L2, const ViewDev *__restrict__ views, int n_views,
+                                  const uint32_t *__restrict__ cage, int cells, const uint32_t *__restrict__ ccage,
+                                  int ccells, int total_tiles, int *counter, SoftIO io, int tw, int th) {
+    int lane = threadIdx.x & 63;
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = atomicAdd(counter, 1);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= total_tiles) return;
+        int lo = 0, hi = n_views - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (views[mid].tile_begin <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewDev &v = views[lo];
+        int lt = tile - v.tile_begin;
+        int x = (lt % v.tiles_x) * tw + lane % tw;
+        int y = (lt / v.tiles_x) * th + lane / tw;
+        // Every lane runs to the end of the body (no per-lane `continue`): the compiler turns
+        // a divergent continue into an inner loop that pops the next tile with only the
+        // continuing lanes active, lane 0 (the popping lane) possibly not among them.
+        if (x < v.W && y < v.H) {
+            const int64_t ray = v.ray_offset + (int64_t)y * v.W + x;
+            float w[3];
+            camera_ray(v, x, y, w);
+            RayResult<float> unused;
+            const uint32_t *cg = cage + (int64_t)lo * cells;
+            const uint32_t *ccg = T == kTwoLevel ? ccage + (int64_t)lo * ccells : nullptr;
+            if constexpr (!Bwd) {
+                SoftFwd f{g, io, 1.0f, {0.0f, 0.0f, 0.0f}};
+                trace_ray<W, T, true>(g, L2, v.pos, w, cg, ccg, unused, f);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) io.rgb[3 * ray + ch] = __fmaf_rn(f.T, g.bg[ch], f.rgb[ch]);
+            } else {
+                SoftBwd b{g, io, w, {io.grad_rgb[3 * ray], io.grad_rgb[3 * ray + 1], io.grad_rgb[3 * ray + 2]},
+                          {io.rgb_fwd[3 * ray], io.rgb_fwd[3 * ray + 1], io.rgb_fwd[3 * ray + 2]}, 1.0f,
+                          {0.0f, 0.0f, 0.0f}};
+                if (b.gr[0] != 0.0f || b.gr[1] != 0.0f || b.gr[2] != 0.0f)
+                    trace_ray<W, T, true>(g, L2, v.pos, w, cg, ccg, unused, b);
+            }
+        }
     }
 }
 
@@ -1000,6 +1112,19 @@ static pt_status trace_impl(const pt_grid *cg, const uint16_t *rad, const pt_vie
     TraceCtx c;
     make_ctx(g, opts, c);
     uint32_t flags = opts ? opts->flags : 0;
+    if (flags & PT_FLAG_FP64) {
+        // one launch per view whatever the launch form asked; no cage tables (every lane
+        // sorts its cages in double)
+        for (int i = 0; i < n_views; ++i) {
+            unsigned nb = (unsigned)((vd[i].tiles_x * ((vd[i].H + th - 1) / th) + 3) / 4);
+#define PT_LAUNCH(W, T) \
+    hipLaunchKernelGGL((k_trace_view_fp64<W, T>), dim3(nb), dim3(256), 0, s, c.d, c.L2, vd[i], rad, o, tw, th)
+            PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
+        }
+        HIP_TRY(hipGetLastError());
+        return PT_OK;
+    }
     if (flags & PT_FLAG_GRAPH) return run_graph(g, c, vd, tiles, rad, o, tw, th, s);
     st = ensure_device(g->cage, g->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
     if (st != PT_OK) return st;
@@ -1087,6 +1212,15 @@ extern "C" pt_status probe_trace_rays(const pt_grid *g, const uint16_t *radiance
     TraceCtx c;
     make_ctx(g, opts, c);
     Outputs o{rgb_dev, t_dev, status_dev, hit_dev};
+    if (opts && (opts->flags & PT_FLAG_FP64)) {
+#define PT_LAUNCH(W, T)                                                                                  \
+    hipLaunchKernelGGL((k_trace_rays_fp64<W, T>), dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, \
+                       c.d, c.L2, origins_dev, dirs_dev, n, radiance_dev, o)
+        PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
+        HIP_TRY(hipGetLastError());
+        return PT_OK;
+    }
 #define PT_LAUNCH(W, T)                                                                                        \
     hipLaunchKernelGGL((k_trace_rays<W, T>), dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c.d, \
                        c.L2, origins_dev, dirs_dev, n, radiance_dev, o)
@@ -1203,6 +1337,63 @@ extern "C" pt_status probe_trace_backward_distance(const pt_grid *g, const uint1
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward_distance: NULL argument");
     AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev};
     return launch_adjoint<true>(g, views_host, n_views, io, opts, stream);
+}
+
+// Soft-visibility forward or adjoint: one persistent launch over the tiles of all views.
+template <bool Bwd>
+static pt_status launch_soft(const pt_grid *g, const pt_view *views_host, int32_t n_views, const SoftIO &io,
+                             const pt_trace_opts *opts, void *stream) {
+    if (!(io.sigma > 0.0f) || !std::isfinite(io.sigma))
+        return fail(PT_ERR_INVALID_ARGUMENT, "soft visibility: sigma must be finite and > 0");
+    int tw, th;
+    pt_status st = tile_shape(opts, tw, th);
+    if (st != PT_OK) return st;
+    std::vector<ViewDev> vd;
+    int64_t rays;
+    int tiles;
+    st = check_views(views_host, n_views, tw, th, vd, rays, tiles);
+    if (st != PT_OK) return st;
+    TraceCtx c;
+    make_ctx(g, opts, c);
+    hipStream_t s = (hipStream_t)stream;
+    pt_grid *mg = const_cast<pt_grid *>(g);
+    st = ensure_device(mg->cage, mg->cage_cap, (int64_t)n_views * std::max(1, g->cells), s, "cage table allocation");
+    if (st != PT_OK) return st;
+    if (c.two) {
+        st = ensure_device(mg->ccage, mg->ccage_cap, (int64_t)n_views * std::max(1, c.ccells), s,
+                           "coarse cage table allocation");
+        if (st != PT_OK) return st;
+    }
+    st = upload_views(mg, vd, s);
+    if (st != PT_OK) return st;
+    launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, mg->counter);
+#define PT_LAUNCH(W, T)                                                                                       \
+    hipLaunchKernelGGL((k_soft_persistent<W, T, Bwd>), dim3(persistent_blocks(g)), dim3(256), 0, s, c.d, c.L2, \
+                       mg->views_dev, n_views, mg->cage, g->cells, mg->ccage, c.ccells, tiles, mg->counter, io, tw, th)
+    PT_DISPATCH(c, PT_LAUNCH);
+#undef PT_LAUNCH
+    HIP_TRY(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status probe_trace_soft(const pt_grid *g, const uint16_t *radiance_dev, const pt_view *views_host,
+                                      int32_t n_views, float sigma, float *rgb_dev, const pt_trace_opts *opts,
+                                      void *stream) {
+    if (!g || !radiance_dev || !rgb_dev) return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_soft: NULL argument");
+    SoftIO io{radiance_dev, sigma, rgb_dev, nullptr, nullptr, nullptr, nullptr};
+    return launch_soft<false>(g, views_host, n_views, io, opts, stream);
+}
+
+extern "C" pt_status probe_trace_soft_backward(const pt_grid *g, const uint16_t *radiance_dev,
+                                               const pt_view *views_host, int32_t n_views, float sigma,
+                                               const float *rgb_dev, const float *grad_rgb_dev,
+                                               float *grad_distance_dev, float *grad_radiance_dev,
+                                               const pt_trace_opts *opts, void *stream) {
+    if (!g || !radiance_dev || !rgb_dev || !grad_rgb_dev || (!grad_distance_dev && !grad_radiance_dev))
+        return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_soft_backward: NULL argument");
+    SoftIO io{radiance_dev, sigma, nullptr, rgb_dev, grad_rgb_dev, grad_distance_dev, grad_radiance_dev};
+    return launch_soft<true>(g, views_host, n_views, io, opts, stream);
 }
 
 // level 0 of every probe from a new distance map, then the MIN pyramid above it

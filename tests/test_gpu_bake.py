@@ -1,6 +1,8 @@
 """Probe baking from a point cloud on the GPU (probe_bake_points) against the oracle's
 definition (oracle/points.py): the nearest point per texel is an integer decision taken in
-FP32 with the same operations on both sides, so the maps must agree bit for bit."""
+FP32 with the same operations on both sides, so the maps must agree bit for bit; and the
+GPU's maps are also held to a double-precision check that shares no part of that recipe
+(a stored distance is never farther than a point binned to its texel in double)."""
 import numpy as np
 import pytest
 import torch
@@ -42,6 +44,23 @@ def test_bake_tiny_room_bit_exact(normals):
     assert np.array_equal(np.isnan(gd), np.isnan(od))
     assert _same(gd, od) and _same(gn, on) and _same(gr, orad)
     assert np.isfinite(od).mean() > 0.9
+    # and, independently of the FP32 recipe both sides share: bin a sample of the points
+    # with the double-precision octahedral map and compare distances in double; the GPU's
+    # stored distance of a texel is at most that of every point binned to it (points within
+    # 1e-5 of a texel edge are left out: FP32 may bin them either way)
+    from oracle.points import probe_origins
+    O = probe_origins(probes.dims, probes.origin, probes.spacing).astype(np.float64)
+    P64 = pts.astype(np.float64)[::11]
+    N = 64
+    for p in range(len(O)):
+        d = P64 - O[p]
+        r = np.linalg.norm(d, axis=1)
+        uv = np.array([oracle.oct_encode(x) for x in d])
+        x, y = (uv[:, 0] + 1) * N / 2, (uv[:, 1] + 1) * N / 2
+        i, j = np.clip(np.floor(x), 0, N - 1).astype(int), np.clip(np.floor(y), 0, N - 1).astype(int)
+        edge = (np.minimum(x - np.floor(x), np.ceil(x) - x) < 1e-5) | (np.minimum(y - np.floor(y), np.ceil(y) - y) < 1e-5)
+        stored = gd[p][j, i].astype(np.float64)
+        assert (edge | (stored <= r * (1 + 1e-6))).all(), p
 
 
 def test_bake_room_sampled_probes_and_tiled_maps():
