@@ -231,3 +231,37 @@ def test_stored_hits_outside_the_grid_add_nothing():
     pt.probe_trace_backward_hits(grid, views[:1], miss, res["t"], gr, b)
     torch.testing.assert_close(a, b, rtol=1e-5, atol=1e-5)
     assert torch.count_nonzero(b).item() > 1000
+
+
+def test_stored_hit_adjoint_with_every_tap_of_a_wave_distinct():
+    # One 8x8 tile (one wavefront) whose 64 rays each name a different probe: its 256 taps are
+    # 256 distinct texels, the most a wave's merge table ever holds; then the same tile with
+    # every ray on one probe and texel (one texel per tap position, heavy merging).  The
+    # expected gradient is the plain definition: for each ray, the 4 bilinear taps at the
+    # direction X - O + t w of its probe, weighted by the upstream gradient.
+    pt, scene, probes, views, grid, rad = _setup("single", size=(64, 64))
+    import synth
+    v = synth.make_views(scene, 41, 1, 8, 8)[0]
+    og = oracle.Grid.from_probes(probes)
+    o, d = oracle.view_rays(*v.as_tuple())
+    N = probes.N
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=(64, 3)).astype(np.float32)
+    for probes_of_rays in (np.arange(64) * 3 % probes.n_probes, np.full(64, 77)):
+        t = rng.uniform(0.5, 3.0, 64).astype(np.float32)
+        hit = np.stack([probes_of_rays, rng.integers(0, N * N, 64)], 1).astype(np.int32)
+        want = np.zeros((probes.n_probes, N * N, 3))
+        for i in range(64):
+            p = int(hit[i, 0])
+            q = o[i] - og.probe_position(p) + float(t[i]) * d[i]
+            u, vv = oracle.oct_encode(q)
+            idx, wt = oracle.bilinear_taps(u, vv, N)
+            for k in range(4):
+                want[p, idx[k]] += wt[k] * g[i].astype(np.float64)
+        gh = torch.zeros((probes.n_probes, N, N, 3), device="cuda")
+        pt.probe_trace_backward_hits(grid, [v], torch.from_numpy(hit).cuda(), torch.from_numpy(t).cuda(),
+                                     torch.from_numpy(g).cuda(), gh)
+        got = gh.cpu().numpy().reshape(probes.n_probes, N * N, 3).astype(np.float64)
+        assert np.count_nonzero(want) > 0
+        assert np.abs(got - want).max() <= 1e-3 * np.abs(g).max(), np.abs(got - want).max()
+        assert np.array_equal(got != 0, want != 0)
