@@ -557,38 +557,40 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
 }
 
 // Wavefront-segmented scatter-add through a table in LDS, for texel indices below 2^32 - 1.
-// Every lane holds up to 4 (texel, rgb) contributions (texel = probe N^2 + j N + i,
-// kEmptyTexel for none).  The wave merges them in its own 256-slot table (an entry takes the
-// first free or matching slot from its hash on, linear probing; 256 slots hold the wave's
-// at most 256 distinct texels), compacts the occupied slots in slot order, and issues the
-// 3 K sums of its K texels as ceil(3 K / 64) FP32 atomic instructions with consecutive lanes
-// on consecutive floats.  Against wave_scatter_add, whose loop runs once per distinct texel
-// (a wave sum, then three single-lane atomics), the cost no longer grows with K in VALU,
-// and a 64-lane atomic instruction over neighbouring texels carried 7x the floats per
-// second of single-lane ones (a probe of both patterns on a 1.6 GB gradient).  The hash
-// keeps the texels of a map row in consecutive slots and spreads neighbouring rows.  All 64
-// lanes must arrive here together; the table is the wave's alone.
+// Every lane holds up to K (texel, C-channel value) contributions (texel = probe N^2 + j N +
+// i, kEmptyTexel for none; the gradient is [texel][C]).  The wave merges them in its own
+// 256-slot table (an entry takes the first free or matching slot from its hash on, linear
+// probing; 256 slots hold the wave's at most 64 K <= 256 distinct texels), compacts the
+// occupied slots in slot order, and issues the C K' sums of its K' texels as ceil(C K' / 64)
+// FP32 atomic instructions with consecutive lanes on consecutive floats.  Against
+// wave_scatter_add, whose loop runs once per distinct texel (a wave sum, then C single-lane
+// atomics), the cost no longer grows with K' in VALU, and a 64-lane atomic instruction over
+// neighbouring texels carried 7x the floats per second of single-lane ones (a probe of both
+// patterns on a 1.6 GB gradient).  The hash keeps the texels of a map row in consecutive
+// slots and spreads neighbouring rows.  All 64 lanes must arrive here together; the table
+// is the wave's alone.
 constexpr uint32_t kEmptyTexel = 0xffffffffu;
 struct WaveTable {
     uint32_t key[256];
     float acc[768];
 };
 
-__device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, const uint32_t tex[4],
-                                                     const float val[4][3], WaveTable &tb, int logN) {
+template <int C, int K>
+__device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, const uint32_t tex[K],
+                                                     const float val[K][C], WaveTable &tb, int logN) {
+    static_assert(C >= 1 && C <= 3 && K >= 1 && K <= 4, "table holds 256 texels of 3 channels");
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int sl = lane + 64 * m;
         tb.key[sl] = kEmptyTexel;
-        tb.acc[3 * sl + 0] = 0.0f;
-        tb.acc[3 * sl + 1] = 0.0f;
-        tb.acc[3 * sl + 2] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) tb.acc[C * sl + c] = 0.0f;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < K; ++k) {
         const uint32_t t = tex[k];
         if (t != kEmptyTexel) {
             uint32_t h = (t + 17u * (t >> logN)) & 255u;
@@ -597,9 +599,8 @@ __device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, c
                 if (old == kEmptyTexel || old == t) break;
                 h = (h + 1u) & 255u;
             }
-            atomicAdd(&tb.acc[3 * h + 0], val[k][0]);
-            atomicAdd(&tb.acc[3 * h + 1], val[k][1]);
-            atomicAdd(&tb.acc[3 * h + 2], val[k][2]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) atomicAdd(&tb.acc[C * h + c], val[k][c]);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -611,26 +612,27 @@ __device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, c
     for (int m = 0; m < 4; ++m) {
         const int sl = lane + 64 * m;
         const uint32_t kk = tb.key[sl];
-        const float a0 = tb.acc[3 * sl], a1 = tb.acc[3 * sl + 1], a2 = tb.acc[3 * sl + 2];
+        float a[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = tb.acc[C * sl + c];
         const bool occ = kk != kEmptyTexel;
         const unsigned long long b = __ballot(occ);
         const int pos = n + __popcll(b & ((1ull << lane) - 1ull));
         __builtin_amdgcn_wave_barrier();
         if (occ) {
             tb.key[pos] = kk;
-            tb.acc[3 * pos + 0] = a0;
-            tb.acc[3 * pos + 1] = a1;
-            tb.acc[3 * pos + 2] = a2;
+#pragma unroll
+            for (int c = 0; c < C; ++c) tb.acc[C * pos + c] = a[c];
         }
         n += __popcll(b);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int d0 = 0; d0 < 3 * n; d0 += 64) {
+    for (int d0 = 0; d0 < C * n; d0 += 64) {
         const int d = d0 + lane;
-        if (d < 3 * n) {
-            const int e = d / 3;
-            atomicAdd(grad + 3 * (int64_t)tb.key[e] + (d - 3 * e), tb.acc[d]);
+        if (d < C * n) {
+            const int e = d / C;
+            atomicAdd(grad + C * (int64_t)tb.key[e] + (d - C * e), tb.acc[d]);
         }
     }
 }
@@ -660,6 +662,7 @@ struct AdjointIO {
     const float *grad_t;
     const uint16_t *rad;
     float *grad_out;
+    int lds_merge;  // merge in LDS (wave_scatter_add_lds); needs texels < 2^32 - 1 over both levels
 };
 
 // One wavefront's tile of an adjoint: recompute the trace, then scatter.  Geo = false:
@@ -696,9 +699,17 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
                 if (val != 0.0f) key = (int64_t)r.probe * g.N * g.N + r.texel;
             }
         }
-        wave_scatter_add1(io.grad_out, key, val);
+        if (io.lds_merge) {
+            __shared__ WaveTable dtables[4];
+            const uint32_t tex[1] = {key >= 0 ? (uint32_t)key : kEmptyTexel};
+            const float v1[1][1] = {{val}};
+            wave_scatter_add_lds<1, 1>(io.grad_out, tex, v1, dtables[threadIdx.x >> 6], g.logN);
+        } else {
+            wave_scatter_add1(io.grad_out, key, val);
+        }
         return;
     }
+    __shared__ WaveTable tables[4];
     int64_t key[4] = {-1, -1, -1, -1};
     float val[4][3] = {};
     const float *__restrict__ grad_rgb = io.grad_rgb;
@@ -716,14 +727,23 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
             int64_t base = (int64_t)r.probe * g.N * g.N;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (wt[k] != 0.0f) key[k] = 3 * (base + idx[k]);
+                if (wt[k] != 0.0f) key[k] = base + idx[k];
                 val[k][0] = wt[k] * gr[0];
                 val[k][1] = wt[k] * gr[1];
                 val[k][2] = wt[k] * gr[2];
             }
         }
     }
-    wave_scatter_add(io.grad_out, key, val);
+    if (io.lds_merge) {
+        uint32_t tex[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tex[k] = key[k] >= 0 ? (uint32_t)key[k] : kEmptyTexel;
+        wave_scatter_add_lds<3, 4>(io.grad_out, tex, val, tables[threadIdx.x >> 6], g.logN);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) key[k] = key[k] >= 0 ? 3 * key[k] : -1;
+        wave_scatter_add(io.grad_out, key, val);
+    }
 }
 
 // Adjoint of one view (radiance or, with Geo, distances); one tile per wavefront.
@@ -817,7 +837,7 @@ __global__ void __launch_bounds__(256) k_backward_hits(GridDev g, Level2 L2, con
         uint32_t tex[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) tex[k] = key[k] >= 0 ? (uint32_t)key[k] : kEmptyTexel;
-        wave_scatter_add_lds(grad_rad, tex, val, tables[threadIdx.x >> 6], g.logN);
+        wave_scatter_add_lds<3, 4>(grad_rad, tex, val, tables[threadIdx.x >> 6], g.logN);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) key[k] = key[k] >= 0 ? 3 * key[k] : -1;
@@ -1378,12 +1398,18 @@ static pt_status launch_adjoint(const pt_grid *g, const pt_view *views_host, int
     return PT_OK;
 }
 
+// The LDS merge of the radiance adjoints keys texels of both levels by a 32-bit index.
+static int lds_merge_fits(const pt_grid *g) {
+    const int64_t texels = (int64_t)(g->P + (g->coarse ? g->coarse->P : 0)) * g->N * g->N;
+    return texels < (int64_t)kEmptyTexel ? 1 : 0;
+}
+
 extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views_host, int32_t n_views,
                                           const float *grad_rgb_dev, float *grad_radiance_dev,
                                           const pt_trace_opts *opts, void *stream) {
     if (!g || !grad_rgb_dev || !grad_radiance_dev)
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
-    AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev};
+    AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev, lds_merge_fits(g)};
     return launch_adjoint<false>(g, views_host, n_views, io, opts, stream);
 }
 
@@ -1409,8 +1435,7 @@ extern "C" pt_status probe_trace_backward_hits(const pt_grid *g, const pt_view *
     st = upload_views(mg, vd, s);
     if (st != PT_OK) return st;
     unsigned nb = blocks_for(tiles, 4);
-    const int64_t texels = (int64_t)(g->P + (c.two ? g->coarse->P : 0)) * g->N * g->N;
-    const int lds_merge = texels < (int64_t)kEmptyTexel ? 1 : 0;
+    const int lds_merge = lds_merge_fits(g);
     if (c.two)
         hipLaunchKernelGGL(k_backward_hits<kTwoLevel>, dim3(nb), dim3(256), 0, s, c.d, c.L2, mg->views_dev, n_views,
                            tiles, tw, th, hit_dev, t_dev, grad_rgb_dev, grad_radiance_dev, lds_merge);
@@ -1428,7 +1453,7 @@ extern "C" pt_status probe_trace_backward_distance(const pt_grid *g, const uint1
                                                    void *stream) {
     if (!g || !grad_distance_dev || (!grad_rgb_dev && !grad_t_dev) || (grad_rgb_dev && !radiance_dev))
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward_distance: NULL argument");
-    AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev};
+    AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev, lds_merge_fits(g)};
     return launch_adjoint<true>(g, views_host, n_views, io, opts, stream);
 }
 

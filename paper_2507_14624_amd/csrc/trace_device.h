@@ -329,13 +329,16 @@ __device__ bool march_piece(const GridDev &g, const float *bp, uint32_t base, co
         R lim = l == 0 ? m2 : m2 * R(1.0000153f);
         if (below(M, lim)) {
             if (l == 0) break;
-            // descend into the child that holds the ray point at t
-            R iL = frcp(fmar(t, s.L1, s.L0));
-            R x = fmar(t, s.A1, s.A0) * iL;
-            R y = fmar(t, s.B1, s.B0) * iL;
+            // descend into the child that holds the ray point at t: the side of the texel's
+            // mid-lines x = c, y = c it lies on, from the signs of A - c L and B - c L at t
+            // (L > 0 on the piece), without dividing
+            const R Lt = fmar(t, s.L1, s.L0);
+            const R At = fmar(t, s.A1, s.A0);
+            const R Bt = fmar(t, s.B1, s.B0);
             --l;
-            I = min(max((int)floor(x) >> l, 2 * I), 2 * I + 1);
-            J = min(max((int)floor(y) >> l, 2 * J), 2 * J + 1);
+            const int cI = (2 * I + 1) << l, cJ = (2 * J + 1) << l;  // level-0 units
+            I = 2 * I + (fmar(-(R)cI, Lt, At) >= R(0.0f) ? 1 : 0);
+            J = 2 * J + (fmar(-(R)cJ, Lt, Bt) >= R(0.0f) ? 1 : 0);
         } else {
             if (!(tmin < s.te) | (--guard < 0)) {  // the piece ends inside this texel
                 l = -1;
