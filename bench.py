@@ -300,8 +300,8 @@ def bake(pt, synth, torch, np, n_points=4_000_000, steps=5):
 
 def paper_maps(pt, synth, torch, np, steps=10):
     """The paper's map configuration: 4 probes (2x2x1, every probe per ray) of 2048^2 maps,
-    the march starting at the 128^2 low-resolution level, one 1920x1080 frame; and, for
-    comparison, the flat march (no low-resolution map)."""
+    the march starting at the 128^2 low-resolution level, one 1920x1080 frame; for
+    comparison the flat march (no low-resolution map), and the trace in double precision."""
     scene, probes, views = synth.workload("paper")
     grid = pt.ProbeGrid.from_probes(probes)
     rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
@@ -312,11 +312,14 @@ def paper_maps(pt, synth, torch, np, steps=10):
     res = {"workload": f"{probes.n_probes} probes (2x2x1) of {probes.N}^2 maps, pyramid to "
                        f"{probes.N >> (probes.levels - 1)}^2; room of {len(scene.obj_type)} objects; "
                        f"1 view of {views[0].width}x{views[0].height}", "rays": rays}
-    for name, lvl in (("low_res_128", probes.levels - 1), ("flat", 0)):
-        opts = pt.trace_opts(tile=(4, 16), start_level=lvl)
+    # the FP32 trace from the low-resolution level and flat, and the double-precision trace
+    # from the low-resolution level (the acceptance mode at these map sizes)
+    for name, lvl, flags in (("low_res_128", probes.levels - 1, 0), ("flat", 0, 0),
+                             ("low_res_128_fp64", probes.levels - 1, pt.PT_FLAG_FP64)):
+        opts = pt.trace_opts(tile=(4, 16), start_level=lvl, flags=flags)
         ms, _ = time_steps(lambda: pt.probe_trace(grid, rad, va, opts, out=out), steps, 2, torch)
         res[name] = {"start_level": lvl, "value": round(rays / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s",
-                     "ms_per_frame": round(ms, 4)}
+                     "ms_per_frame": round(ms, 4), "precision": "f64" if flags else "f32"}
     res["hit_frac"] = round(float((out[2] == 1).float().mean()), 4)
     return res
 

@@ -129,6 +129,12 @@ typedef struct {
                              2048^2 maps meet every few thousand rays) are taken as the
                              double-precision definition takes them.  Several times slower;
                              the adjoints ignore it */
+#define PT_FLAG_SCATTER_PER_TEXEL 128u /* adjoints: reduce a wavefront's contributions per distinct
+                                          texel (a wavefront sum, then one lane's FP32 atomics)
+                                          instead of merging them in an LDS table and spreading
+                                          the atomics over the lanes; the form the library uses
+                                          by itself for grids of 2^32 - 1 texels or more over
+                                          both levels.  Same sums up to FP32 summation order */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 
@@ -236,8 +242,9 @@ pt_status probe_trace_rays(const pt_grid *grid, const uint16_t *radiance_dev, co
  * w_tap * grad_rgb[c] to grad_radiance_dev[p][tap][c] for its 4 bilinear taps.
  *   grad_rgb_dev       [rays][3] FP32, same ray order as probe_trace
  *   grad_radiance_dev  [P][N][N][3] FP32, ACCUMULATED into (+=); caller zeroes it
- * Summation order depends on scheduling (FP32 atomics after an in-wavefront reduction).
- * More than one view, or opts->flags PT_FLAG_PERSISTENT or PT_FLAG_GRAPH: one persistent
+ * Summation order depends on scheduling: each wavefront merges its contributions per texel
+ * (in an LDS table, or per distinct texel with PT_FLAG_SCATTER_PER_TEXEL), then adds the
+ * sums with FP32 atomics.  More than one view, or opts->flags PT_FLAG_PERSISTENT or PT_FLAG_GRAPH: one persistent
  * launch over the tiles of all views (not captured in a graph); otherwise one launch.  With
  * PT_FLAG_NEAREST the single tap is the hit texel.  A grid's calls are stream-ordered
  * state (view tables, tile counter): do not run two calls on one grid concurrently on

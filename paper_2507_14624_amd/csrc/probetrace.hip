@@ -1398,8 +1398,10 @@ static pt_status launch_adjoint(const pt_grid *g, const pt_view *views_host, int
     return PT_OK;
 }
 
-// The LDS merge of the radiance adjoints keys texels of both levels by a 32-bit index.
-static int lds_merge_fits(const pt_grid *g) {
+// The LDS merge of the adjoints keys texels of both levels by a 32-bit index; callers can
+// ask for the per-texel reduction instead.
+static int lds_merge_fits(const pt_grid *g, const pt_trace_opts *opts) {
+    if (opts && (opts->flags & PT_FLAG_SCATTER_PER_TEXEL)) return 0;
     const int64_t texels = (int64_t)(g->P + (g->coarse ? g->coarse->P : 0)) * g->N * g->N;
     return texels < (int64_t)kEmptyTexel ? 1 : 0;
 }
@@ -1409,7 +1411,7 @@ extern "C" pt_status probe_trace_backward(const pt_grid *g, const pt_view *views
                                           const pt_trace_opts *opts, void *stream) {
     if (!g || !grad_rgb_dev || !grad_radiance_dev)
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward: NULL argument");
-    AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev, lds_merge_fits(g)};
+    AdjointIO io{grad_rgb_dev, nullptr, nullptr, grad_radiance_dev, lds_merge_fits(g, opts)};
     return launch_adjoint<false>(g, views_host, n_views, io, opts, stream);
 }
 
@@ -1435,7 +1437,7 @@ extern "C" pt_status probe_trace_backward_hits(const pt_grid *g, const pt_view *
     st = upload_views(mg, vd, s);
     if (st != PT_OK) return st;
     unsigned nb = blocks_for(tiles, 4);
-    const int lds_merge = lds_merge_fits(g);
+    const int lds_merge = lds_merge_fits(g, opts);
     if (c.two)
         hipLaunchKernelGGL(k_backward_hits<kTwoLevel>, dim3(nb), dim3(256), 0, s, c.d, c.L2, mg->views_dev, n_views,
                            tiles, tw, th, hit_dev, t_dev, grad_rgb_dev, grad_radiance_dev, lds_merge);
@@ -1453,7 +1455,7 @@ extern "C" pt_status probe_trace_backward_distance(const pt_grid *g, const uint1
                                                    void *stream) {
     if (!g || !grad_distance_dev || (!grad_rgb_dev && !grad_t_dev) || (grad_rgb_dev && !radiance_dev))
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_backward_distance: NULL argument");
-    AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev, lds_merge_fits(g)};
+    AdjointIO io{grad_rgb_dev, grad_t_dev, radiance_dev, grad_distance_dev, lds_merge_fits(g, opts)};
     return launch_adjoint<true>(g, views_host, n_views, io, opts, stream);
 }
 

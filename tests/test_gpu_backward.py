@@ -176,7 +176,9 @@ def test_adam_reduces_loss_on_small_differentiable_room():
 
 @pytest.mark.parametrize("name,kw,flags", [("single", dict(size=(240, 135)), 0),
                                            ("diff", dict(N=64, levels=4, n_views=3, size=(96, 80)), 0),
-                                           ("tiny", {}, 4)])
+                                           ("tiny", {}, 4),
+                                           ("diff", dict(N=64, levels=4, n_views=3, size=(96, 80)), 128),
+                                           ("single", dict(size=(240, 135)), 128 | 1)])
 def test_backward_from_stored_hits_equals_recompute(name, kw, flags):
     # the adjoint from the forward's (probe, texel) and t outputs rebuilds every sample
     # direction exactly: the same gradient as the recomputing adjoint up to atomic order
@@ -265,3 +267,29 @@ def test_stored_hit_adjoint_with_every_tap_of_a_wave_distinct():
         assert np.count_nonzero(want) > 0
         assert np.abs(got - want).max() <= 1e-3 * np.abs(g).max(), np.abs(got - want).max()
         assert np.array_equal(got != 0, want != 0)
+
+
+def test_per_texel_scatter_matches_oracle_vjp():
+    # the reduction the library keeps for grids of 2^32 - 1 texels or more, forced on a
+    # small grid: the same tolerance against the oracle's VJP as the default LDS merge
+    pt, scene, probes, views, grid, rad = _setup("single", size=(160, 90))
+    _check_grad(pt, probes, grid, rad, views, flags=pt.PT_FLAG_SCATTER_PER_TEXEL)
+    _check_grad(pt, probes, grid, rad, views, flags=pt.PT_FLAG_SCATTER_PER_TEXEL | pt.PT_FLAG_PERSISTENT)
+
+
+def test_per_texel_scatter_equals_lds_merge():
+    # both reductions of the stored-hit adjoint on the differentiable grid, where an 8x8 tile
+    # touches ~100 distinct texels: the same sums up to FP32 summation order
+    pt, scene, probes, views, grid, rad = _setup("diff", N=64, levels=4, n_views=3, size=(128, 96))
+    res = pt.probe_trace(grid, rad, views)
+    rays = res["rgb"].shape[0]
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    gr = torch.randn((rays, 3), generator=gen).cuda()
+    shape = (probes.n_probes, probes.N, probes.N, 3)
+    a = torch.zeros(shape, device="cuda")
+    b = torch.zeros(shape, device="cuda")
+    pt.probe_trace_backward_hits(grid, views, res["hit"], res["t"], gr, a, None)
+    pt.probe_trace_backward_hits(grid, views, res["hit"], res["t"], gr, b,
+                                 pt.trace_opts(flags=pt.PT_FLAG_SCATTER_PER_TEXEL))
+    torch.testing.assert_close(b, a, rtol=1e-5, atol=1e-5)
+    assert torch.count_nonzero(a).item() > 1000

@@ -116,6 +116,15 @@ def test_distance_adjoint_persistent_two_views_t_only_and_rgb_only():
     assert np.count_nonzero(ref_t) > 1000 and np.count_nonzero(ref_c) > 1000
 
 
+def test_distance_adjoint_per_texel_scatter():
+    # the single-channel per-texel reduction (kept for grids of 2^32 - 1 texels or more),
+    # forced: the same oracle tolerance as the LDS merge
+    pt, probes, views, grid, rad, og = _setup("diff", N=64, levels=4, n_views=2, size=(96, 80))
+    _check(pt, probes, views, grid, rad, og, opts=pt.trace_opts(flags=pt.PT_FLAG_SCATTER_PER_TEXEL))
+    _check(pt, probes, views, grid, rad, og,
+           opts=pt.trace_opts(flags=pt.PT_FLAG_SCATTER_PER_TEXEL | pt.PT_FLAG_PERSISTENT))
+
+
 def test_nearest_radiance_does_not_move_with_distance():
     pt, probes, views, grid, rad, og = _setup("tiny")
     opts = pt.trace_opts(flags=pt.PT_FLAG_NEAREST)
