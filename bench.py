@@ -7,7 +7,8 @@ view.  value = rays traced per second (Mrays/s), inputs resident in HBM.
 
 Also reported: forward+backward Mrays/s on the same view (trace + radiance adjoint),
 the batched workload (64 views of uneven size in one persistent hipGraph launch) against
-64 plain launches, the differentiable grid's training step kernel by kernel, the
+64 plain launches, the differentiable grid's training step kernel by kernel, the paper's
+2048^2 maps (FP32 and FP64), the same grid over rooms of 3, 40 and 5,000 objects, the
 two-level city block (8 views of 3840x2160), the HBM roofline of each workload's kernels
 (algorithmic bytes from tests/golden/algorithmic_bytes.json over the measured launch
 time, against 8 TB/s) and the CPU oracle timed on the host.
@@ -392,7 +393,32 @@ def large(pt, synth, torch, np, steps=3):
             "roofline": roof}
 
 
-LEGS = ("fwd_bwd", "batched", "diff", "bake", "paper", "large", "cpu")
+def complexity(pt, synth, torch, np, opts, steps=10):
+    """The same probe grid (8x8x4 probes, 128^2 maps, 5 levels) over rooms of 3, 40 and
+    5,000 objects (seed 1), one 1920x1080 view each (seed 101), the single-view options: the
+    paper reports render times that do not grow with scene complexity."""
+    out = {}
+    for k in (3, 40, 5000):
+        t0 = time.time()
+        scene = synth.make_scene(1, (8, 8, 4), 1.0, (k, k))
+        probes = synth.bake(scene, 128, 5, min(16, os.cpu_count() or 1))
+        bake_s = time.time() - t0
+        views = synth.make_views(scene, 101, 1, 1920, 1080)
+        grid = pt.ProbeGrid.from_probes(probes)
+        rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+        va = pt.make_views(views)
+        rays = pt.n_rays(views)
+        o = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"),
+             torch.empty(rays, dtype=torch.uint8, device="cuda"), None)
+        ms, _ = time_steps(lambda: pt.probe_trace(grid, rad, va, opts, out=o), steps, 3, torch)
+        out[f"objects_{k}"] = {"value": round(rays / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms": round(ms, 4),
+                               "hit_frac": round(float((o[2] == 1).float().mean()), 4),
+                               "host_bake_s": round(bake_s, 1)}
+        del grid, rad, o
+    return out
+
+
+LEGS = ("fwd_bwd", "batched", "diff", "bake", "paper", "complexity", "large", "cpu")
 
 
 def main():
@@ -570,6 +596,9 @@ def main():
     if "paper" in legs:
         print("[bench] paper map configuration", file=sys.stderr, flush=True)
         result["paper_maps"] = paper_maps(pt, synth, torch, np)
+    if "complexity" in legs:
+        print("[bench] scene complexity", file=sys.stderr, flush=True)
+        result["complexity"] = complexity(pt, synth, torch, np, opts)
     if "large" in legs:
         print("[bench] large two-level workload", file=sys.stderr, flush=True)
         result["large"] = large(pt, synth, torch, np)
