@@ -277,26 +277,31 @@ def differentiable(pt, synth, torch, np, steps=5):
 
 
 def bake(pt, synth, torch, np, n_points=4_000_000, steps=5):
-    """Probe maps of the 1080p room (256 probes, 128^2) baked on the GPU from a 4M-point
-    cloud sampled from its surfaces: nearest point per texel, every point against every
-    probe."""
-    scene, probes, views = synth.workload("single", size=(16, 16))
-    pts, col, nrm = synth.sample_points(scene, n_points, 31)
-    pts, col, nrm = (torch.from_numpy(a).cuda() for a in (pts, col, nrm))
-    args = (probes.dims, probes.origin, probes.spacing, probes.N, pts, col, nrm)
-    out = pt.probe_bake_points(*args)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        pt.probe_bake_points(*args)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    pairs = probes.n_probes * n_points
-    return {"workload": f"{probes.n_probes} probes x {probes.N}^2 texels from {n_points} points (1080p room)",
-            "ms": round(ms, 3), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 2),
-            "filled_texels": round(float(torch.isfinite(out[0]).float().mean()), 4)}
+    """Probe maps baked on the GPU from a 4M-point cloud sampled from the scene's surfaces
+    (nearest point per texel): the 1080p room's 256 probes at 128^2 (one tile per map, every
+    point against every probe), and the paper's 4 probes at 2048^2 (256 tiles per map, points
+    binned per probe and tile first)."""
+    res = {}
+    for key, name in (("room", "single"), ("paper_maps", "paper")):
+        scene, probes, views = synth.workload(name, size=(16, 16))
+        pts, col, nrm = synth.sample_points(scene, n_points, 31)
+        pts, col, nrm = (torch.from_numpy(a).cuda() for a in (pts, col, nrm))
+        args = (probes.dims, probes.origin, probes.spacing, probes.N, pts, col, nrm)
+        out = pt.probe_bake_points(*args)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            pt.probe_bake_points(*args)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        pairs = probes.n_probes * n_points
+        res[key] = {"workload": f"{probes.n_probes} probes x {probes.N}^2 texels from {n_points} points",
+                    "ms": round(ms, 3), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 2),
+                    "filled_texels": round(float(torch.isfinite(out[0]).float().mean()), 4)}
+        del out, pts, col, nrm
+    return res
 
 
 def paper_maps(pt, synth, torch, np, steps=10):

@@ -183,8 +183,13 @@ pt_status probe_grid_set_coarse(pt_grid *fine, const pt_grid *coarse, const int3
  * p - O with O = origin + k spacing (one rounding), ties to the smaller point index; the
  * texel of d = p - O is floor((u + 1) N/2) of its octahedral (u, v) with q = d / |d|_1
  * (correctly rounded), clamped to [0, N-1].  Points at a probe centre are skipped.
- * Asynchronous on `stream`; the caller keeps the inputs alive until it has run.
- * Errors: INVALID_ARGUMENT (NULL outputs, bad layout, n_points outside [0, 2^32)), HIP. */
+ * Maps of more than 128^2 texels are baked tile by tile (128^2 each) after the points are
+ * binned by (probe, tile); the bins live in stream-ordered temporary device memory
+ * (hipMallocAsync / hipFreeAsync on `stream`, at most 4 * min(P, 2^28 / n_points) *
+ * n_points bytes plus the counters).  Asynchronous on `stream`; the caller keeps the inputs
+ * alive until it has run.
+ * Errors: INVALID_ARGUMENT (NULL outputs, bad layout, n_points outside [0, 2^32)), HIP
+ * (including a failed temporary allocation). */
 pt_status probe_bake_points(const pt_grid_desc *desc, const float *points_dev, const float *colors_dev,
                             const float *normals_dev, int64_t n_points, float *distance_dev,
                             uint16_t *normal_oct_dev, uint16_t *radiance_dev, void *stream);

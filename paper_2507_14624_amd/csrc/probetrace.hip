@@ -1741,32 +1741,60 @@ extern "C" pt_status probe_autotune(const pt_grid *g, const uint16_t *radiance_d
 // ------------------------------------------------------------------------------------
 // probe baking from a point cloud
 // ------------------------------------------------------------------------------------
+// Texel (i, j) of point m in the map of the probe at O, and its squared distance; false for
+// a point at the probe centre (no direction).
+__device__ __forceinline__ bool bake_texel(const BakeGrid &b, float O0, float O1, float O2,
+                                           const float *__restrict__ pts, int64_t m, int &i, int &j, float &r2) {
+    const float dx = pts[3 * m] - O0, dy = pts[3 * m + 1] - O1, dz = pts[3 * m + 2] - O2;
+    const float L = (fabsf(dx) + fabsf(dy)) + fabsf(dz);
+    if (!(L > 0.0f)) return false;
+    float u, v;
+    bake_oct(dx, dy, dz, u, v);
+    const float hN = (float)(b.N / 2);
+    i = min(max((int)floorf((u + 1.0f) * hN), 0), b.N - 1);
+    j = min(max((int)floorf((v + 1.0f) * hN), 0), b.N - 1);
+    r2 = (dx * dx + dy * dy) + dz * dz;
+    return true;
+}
+
+// probe centre: origin + k spacing, one rounding
+__device__ __forceinline__ void bake_origin(const BakeGrid &b, int p, float &O0, float &O1, float &O2) {
+    const int pi = p % b.n[0], pj = (p / b.n[0]) % b.n[1], pk = p / (b.n[0] * b.n[1]);
+    O0 = __fmaf_rn((float)pi, b.spc[0], b.org[0]);
+    O1 = __fmaf_rn((float)pj, b.spc[1], b.org[1]);
+    O2 = __fmaf_rn((float)pk, b.spc[2], b.org[2]);
+}
+
+// One workgroup per (probe, tile of up to 128 x 128 texels).  Binned = false: every point of
+// the cloud is tested against the tile; Binned = true (maps of more than one tile): only the
+// points k_bake_scatter put in the tile's bin, bins[bin_off[t] .. bin_off[t + 1]) for the t-th
+// (probe, tile) of the batch that starts at probe p0.  Either way the nearest point per texel
+// is the LDS atomic min of (r^2 bits, index) keys, so the result does not depend on the order
+// the points are seen in.
+template <bool Binned>
 __global__ void __launch_bounds__(kBakeThreads)
-    k_bake_points(BakeGrid b, const float *__restrict__ pts, const float *__restrict__ col,
-                  const float *__restrict__ nrm, int64_t M, float *__restrict__ dist, uint32_t *__restrict__ nrm_out,
+    k_bake_points(BakeGrid b, int p0, const float *__restrict__ pts, const float *__restrict__ col,
+                  const float *__restrict__ nrm, int64_t M, const uint32_t *__restrict__ bins,
+                  const uint32_t *__restrict__ bin_off, float *__restrict__ dist, uint32_t *__restrict__ nrm_out,
                   uint16_t *__restrict__ rad) {
     __shared__ unsigned long long key[kBakeTile * kBakeTile];
     const int T = b.tiles, ts = b.ts, N = b.N;
-    const int p = blockIdx.x / (T * T), tt = blockIdx.x % (T * T);
+    const int p = p0 + (int)(blockIdx.x / (T * T)), tt = blockIdx.x % (T * T);
     const int i0 = (tt % T) * ts, j0 = (tt / T) * ts;
-    const int pi = p % b.n[0], pj = (p / b.n[0]) % b.n[1], pk = p / (b.n[0] * b.n[1]);
-    // probe centre: origin + k spacing, one rounding
-    const float O0 = __fmaf_rn((float)pi, b.spc[0], b.org[0]);
-    const float O1 = __fmaf_rn((float)pj, b.spc[1], b.org[1]);
-    const float O2 = __fmaf_rn((float)pk, b.spc[2], b.org[2]);
-    const float hN = (float)(N / 2);
+    float O0, O1, O2;
+    bake_origin(b, p, O0, O1, O2);
     for (int k = threadIdx.x; k < ts * ts; k += blockDim.x) key[k] = ~0ull;
     __syncthreads();
-    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
-        float dx = pts[3 * m] - O0, dy = pts[3 * m + 1] - O1, dz = pts[3 * m + 2] - O2;
-        float L = (fabsf(dx) + fabsf(dy)) + fabsf(dz);
-        if (!(L > 0.0f)) continue;  // at the probe centre: no direction
-        float u, v;
-        bake_oct(dx, dy, dz, u, v);
-        int i = min(max((int)floorf((u + 1.0f) * hN), 0), N - 1) - i0;
-        int j = min(max((int)floorf((v + 1.0f) * hN), 0), N - 1) - j0;
+    const int64_t e0 = Binned ? (int64_t)bin_off[blockIdx.x] : 0;
+    const int64_t e1 = Binned ? (int64_t)bin_off[blockIdx.x + 1] : M;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int64_t m = Binned ? (int64_t)bins[e] : e;
+        int i, j;
+        float r2;
+        if (!bake_texel(b, O0, O1, O2, pts, m, i, j, r2)) continue;
+        i -= i0;
+        j -= j0;
         if ((unsigned)i >= (unsigned)ts || (unsigned)j >= (unsigned)ts) continue;  // another tile
-        float r2 = (dx * dx + dy * dy) + dz * dz;
         unsigned long long k = ((unsigned long long)__float_as_uint(r2) << 32) | (unsigned long long)(uint32_t)m;
         atomicMin(&key[j * ts + i], k);
     }
@@ -1803,6 +1831,74 @@ __global__ void __launch_bounds__(kBakeThreads)
     }
 }
 
+// Binning of a batch of probes [p0, p0 + gridDim.y) for maps of more than one tile (at
+// most 1024 tiles): the tile of point m in probe p0 + blockIdx.y's map, by the same texel
+// test as k_bake_points, so every point lands in the bin of the tile that keeps it.  Each
+// workgroup first counts its points per tile in LDS (neighbouring points mostly share a
+// tile, so one global atomic per tile and workgroup replaces one per point).  Scatter =
+// false adds the counts to cnt; Scatter = true reserves the workgroup's range of each bin
+// from the cursors cnt (the exclusive prefix sums of the counts) and writes its points
+// there, a second pass over the same points placing each with an LDS atomic.
+template <bool Scatter>
+__global__ void __launch_bounds__(256) k_bake_bin(BakeGrid b, int p0, const float *__restrict__ pts, int64_t M,
+                                                  uint32_t *__restrict__ cnt, uint32_t *__restrict__ bins) {
+    __shared__ uint32_t hist[1024];
+    const int T = b.tiles, ts = b.ts, T2 = T * T;
+    const int pl = blockIdx.y;
+    float O0, O1, O2;
+    bake_origin(b, p0 + pl, O0, O1, O2);
+    for (int k = threadIdx.x; k < T2; k += blockDim.x) hist[k] = 0u;
+    __syncthreads();
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t m = first; m < M; m += stride) {
+        int i, j;
+        float r2;
+        if (bake_texel(b, O0, O1, O2, pts, m, i, j, r2)) atomicAdd(&hist[(j / ts) * T + i / ts], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < T2; k += blockDim.x) {
+        const uint32_t c = hist[k];
+        if (!Scatter) {
+            if (c) atomicAdd(&cnt[pl * T2 + k], c);
+        } else {
+            hist[k] = c ? atomicAdd(&cnt[pl * T2 + k], c) : 0u;  // the workgroup's range starts here
+        }
+    }
+    if (!Scatter) return;
+    __syncthreads();
+    for (int64_t m = first; m < M; m += stride) {
+        int i, j;
+        float r2;
+        if (bake_texel(b, O0, O1, O2, pts, m, i, j, r2)) bins[atomicAdd(&hist[(j / ts) * T + i / ts], 1u)] = (uint32_t)m;
+    }
+}
+
+// Exclusive prefix sums of n counts (one workgroup of 1024 threads, n <= 2^20): off[0..n],
+// and a copy of off[0..n) in cur for the scatter's cursors.
+__global__ void __launch_bounds__(1024) k_bake_scan(const uint32_t *__restrict__ cnt, int n, uint32_t *__restrict__ off,
+                                                    uint32_t *__restrict__ cur) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x, chunk = (n + 1023) / 1024;
+    const int lo = min(t * chunk, n), hi = min(lo + chunk, n);
+    uint32_t sum = 0;
+    for (int k = lo; k < hi; ++k) sum += cnt[k];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the chunk sums
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int k = lo; k < hi; ++k) {
+        off[k] = run;
+        cur[k] = run;
+        run += cnt[k];
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
 extern "C" pt_status probe_bake_points(const pt_grid_desc *desc, const float *points_dev, const float *colors_dev,
                                        const float *normals_dev, int64_t n_points, float *distance_dev,
                                        uint16_t *normal_oct_dev, uint16_t *radiance_dev, void *stream) {
@@ -1832,8 +1928,45 @@ extern "C" pt_status probe_bake_points(const pt_grid_desc *desc, const float *po
     b.tiles = N / b.ts;
     int64_t blocks = P * b.tiles * b.tiles;
     if (blocks > INT32_MAX) return fail(PT_ERR_INVALID_ARGUMENT, "probe_bake_points: too many probes x tiles");
-    hipLaunchKernelGGL(k_bake_points, dim3((unsigned)blocks), dim3(kBakeThreads), 0, (hipStream_t)stream, b, points_dev,
-                       colors_dev, normals_dev, n_points, distance_dev, (uint32_t *)normal_oct_dev, radiance_dev);
-    HIP_TRY(hipGetLastError());
+    hipStream_t s = (hipStream_t)stream;
+    const int T2 = b.tiles * b.tiles;
+    if (T2 == 1 || n_points == 0) {  // one tile per map: every workgroup reads the whole cloud
+        hipLaunchKernelGGL(k_bake_points<false>, dim3((unsigned)blocks), dim3(kBakeThreads), 0, s, b, 0, points_dev,
+                           colors_dev, normals_dev, n_points, nullptr, nullptr, distance_dev,
+                           (uint32_t *)normal_oct_dev, radiance_dev);
+        HIP_TRY(hipGetLastError());
+        return PT_OK;
+    }
+    // Maps of several tiles: bin the points by (probe, tile) first, so that each tile's
+    // workgroup reads only its own points (a full pass over the cloud per probe instead of
+    // one per tile).  Probes go in batches whose bins take at most 2^28 entries (1 GiB),
+    // whose (probe, tile) count fits the one-workgroup scan, and which fit the grid's y size.
+    const int64_t batch = std::max<int64_t>(
+        1, std::min<int64_t>({P, ((int64_t)1 << 28) / n_points, ((int64_t)1 << 20) / T2, (int64_t)65535}));
+    const int64_t nb = batch * T2;
+    uint32_t *tmp = nullptr;
+    const size_t words = (size_t)(3 * nb + 1) + (size_t)(batch * n_points);
+    HIP_TRY(hipMallocAsync((void **)&tmp, words * sizeof(uint32_t), s));
+    uint32_t *cnt = tmp, *off = tmp + nb, *cur = tmp + 2 * nb + 1, *bins = tmp + 3 * nb + 1;
+    // binning workgroups per probe: about 16 points per thread, at most 1024
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_points + 4095) / 4096, 1024));
+    hipError_t err = hipSuccess;
+    for (int64_t p0 = 0; p0 < P && err == hipSuccess; p0 += batch) {
+        const int np = (int)std::min<int64_t>(batch, P - p0);
+        err = hipMemsetAsync(cnt, 0, (size_t)np * T2 * sizeof(uint32_t), s);
+        if (err != hipSuccess) break;
+        hipLaunchKernelGGL(k_bake_bin<false>, dim3(gx, (unsigned)np), dim3(256), 0, s, b, (int)p0, points_dev,
+                           n_points, cnt, nullptr);
+        hipLaunchKernelGGL(k_bake_scan, dim3(1), dim3(1024), 0, s, cnt, np * T2, off, cur);
+        hipLaunchKernelGGL(k_bake_bin<true>, dim3(gx, (unsigned)np), dim3(256), 0, s, b, (int)p0, points_dev,
+                           n_points, cur, bins);
+        hipLaunchKernelGGL(k_bake_points<true>, dim3((unsigned)(np * T2)), dim3(kBakeThreads), 0, s, b, (int)p0,
+                           points_dev, colors_dev, normals_dev, n_points, bins, off, distance_dev,
+                           (uint32_t *)normal_oct_dev, radiance_dev);
+        err = hipGetLastError();
+    }
+    const hipError_t ferr = hipFreeAsync(tmp, s);
+    HIP_TRY(err);
+    HIP_TRY(ferr);
     return PT_OK;
 }

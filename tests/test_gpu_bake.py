@@ -64,15 +64,29 @@ def test_bake_tiny_room_bit_exact(normals):
 
 
 def test_bake_room_sampled_probes_and_tiled_maps():
-    # 256 probes at 128^2 (one LDS tile per map) and 256^2 maps (four tiles per map); the
-    # oracle bakes a sample of the probes
+    # 256 probes at 128^2 (one LDS tile per map: every workgroup reads the whole cloud) and
+    # 256^2 maps (four tiles per map: the points are binned per probe and tile first, and
+    # 256 probes x 1.2M points take two batches of bins); the oracle bakes a sample of the
+    # probes, from both batches
     scene, probes, views = workload("single", size=(64, 64))
-    pts, col, nrm = synth.sample_points(scene, 1_000_000, 22)
+    pts, col, nrm = synth.sample_points(scene, 1_200_000, 22)
     sel = np.array([0, 17, 100, 133, 200, 255])
     for N in (128, 256):
         gd, gn, gr = _gpu_bake(probes, N, pts, col, nrm)
         od, on, orad, win = bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm, probes=sel)
         assert _same(gd[sel], od) and _same(gn[sel], on) and _same(gr[sel], orad), N
+
+
+@pytest.mark.parametrize("name,N,n_points", [("tiny", 512, 300_000), ("paper", 2048, 2_000_000)])
+def test_bake_binned_large_maps_bit_exact(name, N, n_points):
+    # maps of 16 x 16 tiles (512^2 over 128^2 tiles) and the paper's 2048^2 maps (256 tiles
+    # per map): the binned bake against the oracle's definition, every probe
+    scene, probes, views = workload(name, size=(64, 64))
+    pts, col, nrm = synth.sample_points(scene, n_points, 23)
+    gd, gn, gr = _gpu_bake(probes, N, pts, col, nrm)
+    od, on, orad, win = bake_points(probes.dims, probes.origin, probes.spacing, N, pts, col, nrm)
+    assert _same(gd, od) and _same(gn, on) and _same(gr, orad)
+    assert np.isfinite(od).mean() > 0.2
 
 
 def test_bake_empty_cloud_and_bad_arguments():
