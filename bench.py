@@ -5,7 +5,8 @@ One step = one full trace of the single-view workload: a seeded synthetic room o
 (FP32 distance, FP16 normal and radiance, 5-level MIN pyramid), one 1920x1080 pinhole
 view.  value = rays traced per second (Mrays/s), inputs resident in HBM.
 
-Also reported: forward+backward Mrays/s on the same view (trace + radiance adjoint),
+Also reported: forward+backward Mrays/s on the same view (trace + radiance adjoint; the
+soft-visibility trace and its adjoint),
 the batched workload (64 views of uneven size in one persistent hipGraph launch) against
 64 plain launches, the differentiable grid's training step kernel by kernel, the paper's
 2048^2 maps (FP32 and FP64), the same grid over rooms of 3, 40 and 5,000 objects, the
@@ -569,6 +570,24 @@ def main():
                              max(3, args.steps // 2), 1, torch)
         result["fwd_bwd_stored_hits"]["adjoint_roofline"] = hbm_roof(ab["adjoint_stored_hits_total_bytes"], ms_a,
                                                                      "k_backward_hits<0>")
+        # soft visibility on the same view: the relaxed forward, and forward + its adjoint
+        # into both the distances and the radiance
+        sigma = 0.05
+        srgb = torch.empty((rays, 3), device="cuda")
+        gdist = torch.zeros((probes.n_probes, probes.N, probes.N), device="cuda")
+        ms_sf, _ = time_steps(lambda: pt.probe_trace_soft(grid, rad, va, sigma, opts, out=srgb),
+                              max(3, args.steps // 2), 1, torch)
+
+        def soft_fwd_bwd():
+            pt.probe_trace_soft(grid, rad, va, sigma, opts, out=srgb)
+            pt.probe_trace_soft_backward(grid, rad, va, sigma, srgb, gout, gdist, grad, opts)
+
+        ms_sb, _ = time_steps(soft_fwd_bwd, max(3, args.steps // 2), 1, torch)
+        result["soft"] = {"sigma": sigma,
+                          "fwd": {"value": round(rays / (ms_sf * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                                  "ms": round(ms_sf, 4)},
+                          "fwd_bwd": {"value": round(rays / (ms_sb * 1e-3) / 1e6, 3), "unit": "Mrays/s",
+                                      "ms": round(ms_sb, 4), "adjoint": "distances and radiance"}}
     if "batched" in legs:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         _, _, bviews = synth.workload("batched")

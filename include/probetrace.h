@@ -130,11 +130,12 @@ typedef struct {
                              double-precision definition takes them.  Several times slower;
                              the adjoints ignore it */
 #define PT_FLAG_SCATTER_PER_TEXEL 128u /* adjoints: reduce a wavefront's contributions per distinct
-                                          texel (a wavefront sum, then one lane's FP32 atomics)
-                                          instead of merging them in an LDS table and spreading
-                                          the atomics over the lanes; the form the library uses
-                                          by itself for grids of 2^32 - 1 texels or more over
-                                          both levels.  Same sums up to FP32 summation order */
+                                          texel (a wavefront sum, then one lane's FP32 atomics;
+                                          the soft adjoint: each lane's own atomics) instead of
+                                          merging them in an LDS table and spreading the atomics
+                                          over the lanes; the form the library uses by itself
+                                          for grids of 2^32 - 1 texels or more over both levels.
+                                          Same sums up to FP32 summation order */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 
@@ -328,8 +329,10 @@ pt_status probe_trace_soft(const pt_grid *grid, const uint16_t *radiance_dev, co
  *   grad_rgb_dev       [rays][3] FP32
  *   grad_distance_dev  [P][N][N] FP32, ACCUMULATED (+=), or NULL
  *   grad_radiance_dev  [P][N][N][3] FP32, ACCUMULATED (+=), or NULL (not both NULL)
- * In a two-level hierarchy P counts both levels, fine first.  FP32 atomics per candidate
- * (summation order depends on scheduling).  Errors: INVALID_ARGUMENT, HIP. */
+ * In a two-level hierarchy P counts both levels, fine first.  A ray's first two candidates
+ * are merged per texel across the wavefront and added with FP32 atomics (each lane's own
+ * atomics with PT_FLAG_SCATTER_PER_TEXEL, and for later candidates); summation order
+ * depends on scheduling.  Errors: INVALID_ARGUMENT, HIP. */
 pt_status probe_trace_soft_backward(const pt_grid *grid, const uint16_t *radiance_dev, const pt_view *views_host,
                                     int32_t n_views, float sigma, const float *rgb_dev, const float *grad_rgb_dev,
                                     float *grad_distance_dev, float *grad_radiance_dev, const pt_trace_opts *opts,

@@ -570,15 +570,16 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
 // slots and spreads neighbouring rows.  All 64 lanes must arrive here together; the table
 // is the wave's alone.
 constexpr uint32_t kEmptyTexel = 0xffffffffu;
-struct WaveTable {
+template <int C>
+struct WaveTableC {
     uint32_t key[256];
-    float acc[768];
+    float acc[256 * C];
 };
+using WaveTable = WaveTableC<3>;
 
-template <int C, int K>
-__device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, const uint32_t tex[K],
-                                                     const float val[K][C], WaveTable &tb, int logN) {
-    static_assert(C >= 1 && C <= 3 && K >= 1 && K <= 4, "table holds 256 texels of 3 channels");
+// All 64 lanes: empty the table (the wave's alone).
+template <int C>
+__device__ __forceinline__ void wave_table_clear(WaveTableC<C> &tb) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -589,24 +590,30 @@ __device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, c
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const uint32_t t = tex[k];
-        if (t != kEmptyTexel) {
-            uint32_t h = (t + 17u * (t >> logN)) & 255u;
-            for (;;) {
-                const uint32_t old = atomicCAS(&tb.key[h], kEmptyTexel, t);
-                if (old == kEmptyTexel || old == t) break;
-                h = (h + 1u) & 255u;
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) atomicAdd(&tb.acc[C * h + c], val[k][c]);
-        }
+}
+
+// One lane: the slot of texel t (taken if free), trying at most `tries` slots from its hash
+// on; -1 if none is free.  The hash keeps the texels of a map row in consecutive slots and
+// spreads neighbouring rows.
+template <int C>
+__device__ __forceinline__ int wave_table_slot(WaveTableC<C> &tb, uint32_t t, int logN, int tries) {
+    uint32_t h = (t + 17u * (t >> logN)) & 255u;
+    for (int k = 0; k < tries; ++k) {
+        const uint32_t old = atomicCAS(&tb.key[h], kEmptyTexel, t);
+        if (old == kEmptyTexel || old == t) return (int)h;
+        h = (h + 1u) & 255u;
     }
+    return -1;
+}
+
+// All 64 lanes: move the occupied slots to the front, in slot order; returns their number.
+// Slot s moves to the number of occupied slots before it (<= s), and every round reads its
+// 64 slots before it writes.
+template <int C>
+__device__ __forceinline__ int wave_table_compact(WaveTableC<C> &tb) {
+    const int lane = threadIdx.x & 63;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // compact in place: slot s moves to the number of occupied slots before it (<= s), and
-    // every round reads its 64 slots before it writes
     int n = 0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -628,11 +635,83 @@ __device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, c
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    return n;
+}
+
+// Wavefront-segmented scatter-add through the LDS table, for texel indices below 2^32 - 1.
+// Every lane holds up to K (texel, C-channel value) contributions (texel = probe N^2 + j N +
+// i, kEmptyTexel for none; the gradient is [texel][C]).  The wave merges them in its own
+// 256-slot table (at most 64 K <= 256 distinct texels, so every one finds a slot), compacts
+// the occupied slots, and issues the C K' sums of its K' texels as ceil(C K' / 64) FP32
+// atomic instructions with consecutive lanes on consecutive floats.  Against
+// wave_scatter_add, whose loop runs once per distinct texel (a wave sum, then C single-lane
+// atomics), the cost no longer grows with K' in VALU, and a 64-lane atomic instruction over
+// neighbouring texels carried 7x the floats per second of single-lane ones (a probe of both
+// patterns on a 1.6 GB gradient).  All 64 lanes must arrive here together.
+template <int C, int K>
+__device__ __forceinline__ void wave_scatter_add_lds(float *__restrict__ grad, const uint32_t tex[K],
+                                                     const float val[K][C], WaveTableC<C> &tb, int logN) {
+    static_assert(C >= 1 && K >= 1 && K <= 4, "the table holds 256 texels");
+    const int lane = threadIdx.x & 63;
+    wave_table_clear(tb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (tex[k] != kEmptyTexel) {
+            const int h = wave_table_slot(tb, tex[k], logN, 256);  // >= 0: at most 256 texels
+            if (h >= 0) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) atomicAdd(&tb.acc[C * h + c], val[k][c]);
+            }
+        }
+    }
+    const int n = wave_table_compact(tb);
     for (int d0 = 0; d0 < C * n; d0 += 64) {
         const int d = d0 + lane;
         if (d < C * n) {
             const int e = d / C;
             atomicAdd(grad + C * (int64_t)tb.key[e] + (d - C * e), tb.acc[d]);
+        }
+    }
+}
+
+// The soft adjoint's wavefront-merging sink (SoftBwd): each lane adds a texel's radiance (3)
+// and distance (1) gradients into the wave's 4-channel LDS table on its own, during its
+// divergent walk; a contribution that finds no slot among kSoftTries adds with FP32 atomics.
+// soft_flush (all 64 lanes, after the walk) adds the table to the gradients.
+constexpr int kSoftTries = 32;
+struct SoftLdsSink {
+    WaveTableC<4> &tb;
+    float *grad_dist, *grad_rad;
+    int logN;
+    __device__ void add(int64_t texel, const float rgb[3], float d) {
+        const int h = wave_table_slot(tb, (uint32_t)texel, logN, kSoftTries);
+        if (h < 0) {
+            SoftAtomicSink{grad_dist, grad_rad}.add(texel, rgb, d);
+            return;
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            if (rgb[ch] != 0.0f) atomicAdd(&tb.acc[4 * h + ch], rgb[ch]);
+        if (d != 0.0f) atomicAdd(&tb.acc[4 * h + 3], d);
+    }
+};
+
+__device__ __forceinline__ void soft_flush(WaveTableC<4> &tb, float *__restrict__ grad_dist,
+                                           float *__restrict__ grad_rad) {
+    const int lane = threadIdx.x & 63;
+    const int n = wave_table_compact(tb);
+    for (int d0 = 0; d0 < 4 * n; d0 += 64) {
+        const int d = d0 + lane;
+        if (d < 4 * n) {
+            const int e = d >> 2, c = d & 3;
+            const float v = tb.acc[d];
+            if (v != 0.0f) {
+                if (c < 3) {
+                    if (grad_rad) atomicAdd(grad_rad + 3 * (int64_t)tb.key[e] + c, v);
+                } else if (grad_dist) {
+                    atomicAdd(grad_dist + (int64_t)tb.key[e], v);
+                }
+            }
         }
     }
 }
@@ -700,7 +779,7 @@ __device__ __forceinline__ void backward_tile(const GridDev &g, const Level2 &L2
             }
         }
         if (io.lds_merge) {
-            __shared__ WaveTable dtables[4];
+            __shared__ WaveTableC<1> dtables[4];
             const uint32_t tex[1] = {key >= 0 ? (uint32_t)key : kEmptyTexel};
             const float v1[1][1] = {{val}};
             wave_scatter_add_lds<1, 1>(io.grad_out, tex, v1, dtables[threadIdx.x >> 6], g.logN);
@@ -892,6 +971,14 @@ PT_TRACE_KERNEL k_soft_persistent(GridDev g, Level2 L2, const ViewDev *__restric
         int lt = tile - v.tile_begin;
         int x = (lt % v.tiles_x) * tw + lane % tw;
         int y = (lt / v.tiles_x) * th + lane / tw;
+        // Bwd with io.merge: the wave's table of this tile's gradients (SoftLdsSink), cleared
+        // and flushed by all 64 lanes around the walk
+        [[maybe_unused]] WaveTableC<4> *tb = nullptr;
+        if constexpr (Bwd) {
+            __shared__ WaveTableC<4> tables[4];
+            tb = &tables[threadIdx.x >> 6];
+            if (io.merge) wave_table_clear(*tb);  // the same for every lane
+        }
         // Every lane runs to the end of the body (no per-lane `continue`): the compiler turns
         // a divergent continue into an inner loop that pops the next tile with only the
         // continuing lanes active, lane 0 (the popping lane) possibly not among them.
@@ -908,12 +995,25 @@ PT_TRACE_KERNEL k_soft_persistent(GridDev g, Level2 L2, const ViewDev *__restric
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) io.rgb[3 * ray + ch] = __fmaf_rn(f.T, g.bg[ch], f.rgb[ch]);
             } else {
-                SoftBwd b{g, io, w, {io.grad_rgb[3 * ray], io.grad_rgb[3 * ray + 1], io.grad_rgb[3 * ray + 2]},
-                          {io.rgb_fwd[3 * ray], io.rgb_fwd[3 * ray + 1], io.rgb_fwd[3 * ray + 2]}, 1.0f,
-                          {0.0f, 0.0f, 0.0f}};
-                if (b.gr[0] != 0.0f || b.gr[1] != 0.0f || b.gr[2] != 0.0f)
-                    trace_ray<W, T, true>(g, L2, v.pos, w, cg, ccg, unused, b);
+                const float gr[3] = {io.grad_rgb[3 * ray], io.grad_rgb[3 * ray + 1], io.grad_rgb[3 * ray + 2]};
+                const float rgb[3] = {io.rgb_fwd[3 * ray], io.rgb_fwd[3 * ray + 1], io.rgb_fwd[3 * ray + 2]};
+                if (gr[0] != 0.0f || gr[1] != 0.0f || gr[2] != 0.0f) {
+                    if (io.merge) {
+                        SoftLdsSink sink{*tb, io.grad_dist, io.grad_rad, g.logN};
+                        SoftBwd<SoftLdsSink> b{g, io, w, {gr[0], gr[1], gr[2]}, {rgb[0], rgb[1], rgb[2]}, 1.0f,
+                                               {0.0f, 0.0f, 0.0f}, sink};
+                        trace_ray<W, T, true>(g, L2, v.pos, w, cg, ccg, unused, b);
+                    } else {
+                        SoftAtomicSink sink{io.grad_dist, io.grad_rad};
+                        SoftBwd<SoftAtomicSink> b{g, io, w, {gr[0], gr[1], gr[2]}, {rgb[0], rgb[1], rgb[2]}, 1.0f,
+                                                  {0.0f, 0.0f, 0.0f}, sink};
+                        trace_ray<W, T, true>(g, L2, v.pos, w, cg, ccg, unused, b);
+                    }
+                }
             }
+        }
+        if constexpr (Bwd) {
+            if (io.merge) soft_flush(*tb, io.grad_dist, io.grad_rad);
         }
     }
 }
@@ -1512,7 +1612,8 @@ extern "C" pt_status probe_trace_soft_backward(const pt_grid *g, const uint16_t 
                                                const pt_trace_opts *opts, void *stream) {
     if (!g || !radiance_dev || !rgb_dev || !grad_rgb_dev || (!grad_distance_dev && !grad_radiance_dev))
         return fail(PT_ERR_INVALID_ARGUMENT, "probe_trace_soft_backward: NULL argument");
-    SoftIO io{radiance_dev, sigma, nullptr, rgb_dev, grad_rgb_dev, grad_distance_dev, grad_radiance_dev};
+    SoftIO io{radiance_dev, sigma, nullptr, rgb_dev, grad_rgb_dev, grad_distance_dev, grad_radiance_dev,
+              lds_merge_fits(g, opts)};
     return launch_soft<true>(g, views_host, n_views, io, opts, stream);
 }
 

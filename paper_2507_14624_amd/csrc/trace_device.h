@@ -972,6 +972,23 @@ struct SoftIO {
     const float *grad_rgb; // backward: upstream gradient [rays][3]
     float *grad_dist;      // backward: += into [P][N][N] (nullable)
     float *grad_rad;       // backward: += into [P][N][N][3] (nullable)
+    int merge;             // backward: merge per texel in the wavefront's LDS table (the
+                           // kernel's sink) instead of FP32 atomics per lane
+};
+
+// Where the soft adjoint's contributions go: add(texel, rgb, d) adds rgb to the radiance
+// gradient of texel (probe N^2 + j N + i over both levels) and d to its distance gradient.
+// This one adds with FP32 atomics per lane.
+struct SoftAtomicSink {
+    float *grad_dist, *grad_rad;
+    __device__ void add(int64_t texel, const float rgb[3], float d) {
+        if (grad_rad) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                if (rgb[ch] != 0.0f) atomicAdd(grad_rad + 3 * texel + ch, rgb[ch]);
+        }
+        if (grad_dist && d != 0.0f) atomicAdd(grad_dist + texel, d);
+    }
 };
 
 // acceptance weight of a candidate and the derivative of its logistic argument by r
@@ -1010,13 +1027,15 @@ struct SoftFwd {
 //   dL/dx_j = g . (w_j (1 - a_j) c_j - a_j (rgb - A_j)),
 //   dL/dr_j = dL/dx_j dx_j/dr_j + w_j (g . dc_j/dt) dt_j/dr_j   (the candidate's texel),
 //   dL/dRad = w_j * bilinear weight * g                          (the candidate's taps),
-// FP32 atomics per lane (the soft path is not the hot path).
+// each handed to the sink (SoftAtomicSink, or the kernel's wavefront-merging one).
+template <class Sink>
 struct SoftBwd {
     const GridDev &g;
     const SoftIO &io;
     const float *w;     // ray direction
     float gr[3], rgb[3];
     float P, A[3];
+    Sink &sink;
     __device__ bool operator()(const GridDev &, const RayResult<float> &c, const ProbeResult<float> &pr) {
         float dxdr;
         const float a = soft_accept(g, io.sigma, pr, dxdr);
@@ -1038,17 +1057,16 @@ struct SoftBwd {
             float geo = wj * __fmaf_rn(gr[2], drgb[2], __fmaf_rn(gr[1], drgb[1], gr[0] * drgb[0])) * c.dtdr;
             if (wj == 0.0f || !isfinite(geo)) geo = 0.0f;  // dt/dr is infinite at a tangency
             const float v = __fmaf_rn(dx, dxdr, geo);
-            if (v != 0.0f) atomicAdd(io.grad_dist + (int64_t)c.probe * NN + c.texel, v);
+            const float none[3] = {0.0f, 0.0f, 0.0f};
+            if (v != 0.0f) sink.add((int64_t)c.probe * NN + c.texel, none, v);
         }
         if (io.grad_rad && wj != 0.0f) {
-            float *G = io.grad_rad + (int64_t)c.probe * NN * 3;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (wt[k] == 0.0f) continue;
-                const float s = wj * wt[k];
-                atomicAdd(G + 3 * idx[k] + 0, s * gr[0]);
-                atomicAdd(G + 3 * idx[k] + 1, s * gr[1]);
-                atomicAdd(G + 3 * idx[k] + 2, s * gr[2]);
+                const float sw = wj * wt[k];
+                const float v3[3] = {sw * gr[0], sw * gr[1], sw * gr[2]};
+                sink.add((int64_t)c.probe * NN + idx[k], v3, 0.0f);
             }
         }
         P *= 1.0f - a;

@@ -62,7 +62,7 @@ def test_soft_hard_limit():
     assert diff[clear].max() <= 1e-6, diff[clear].max()
 
 
-def _grad_case(name, rel, **kw):
+def _grad_case(name, rel, flags=0, **kw):
     pt, probes, views, grid, rad, og, o, d = _setup(name, **kw)
     sigma = rel * 8.0 / probes.N
     orc = oracle.trace_soft(og, o, d, sigma)
@@ -74,13 +74,19 @@ def _grad_case(name, rel, **kw):
     P, N = probes.n_probes, probes.N
     gd = torch.zeros((P, N, N), device="cuda")
     gr = torch.zeros((P, N, N, 3), device="cuda")
-    pt.probe_trace_soft_backward(grid, rad, views, sigma, rgb, torch.from_numpy(g.astype(np.float32)).cuda(), gd, gr)
+    opts = pt.trace_opts(flags=flags) if flags else None
+    pt.probe_trace_soft_backward(grid, rad, views, sigma, rgb, torch.from_numpy(g.astype(np.float32)).cuda(), gd, gr,
+                                 opts)
     return gd.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64), gd_o, gr_o
 
 
-@pytest.mark.parametrize("name,kw,rel", [("tiny", {}, 0.5), ("single", dict(size=(240, 135)), 0.25)])
-def test_soft_gradients_match_oracle(name, kw, rel):
-    gd, gr, gd_o, gr_o = _grad_case(name, rel, **kw)
+# flags 128 = PT_FLAG_SCATTER_PER_TEXEL: every candidate adds with its lane's own atomics
+# instead of the wavefront-merged scatter of the first two
+@pytest.mark.parametrize("name,kw,rel,flags", [("tiny", {}, 0.5, 0), ("single", dict(size=(240, 135)), 0.25, 0),
+                                               ("single", dict(size=(240, 135)), 0.25, 128),
+                                               ("diff", dict(N=64, levels=4, n_views=2, size=(96, 80)), 0.25, 0)])
+def test_soft_gradients_match_oracle(name, kw, rel, flags):
+    gd, gr, gd_o, gr_o = _grad_case(name, rel, flags, **kw)
     for label, got, ref in (("distance", gd, gd_o), ("radiance", gr, gr_o)):
         scale = np.abs(ref).max()
         err = np.abs(got - ref)
