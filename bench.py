@@ -100,7 +100,7 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(probes, view):
+def cpu_baseline(probes, view, large_kept=None):
     import numpy as np
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -125,13 +125,14 @@ def cpu_baseline(probes, view):
                        f"{dt:.1f} s", bytes_per_ray=float(oracle.algorithmic_bytes(r).mean()),
                 one_thread={"value": len(o[::8]) / dt1 / 1e6, "unit": "Mrays/s",
                             "sample": f"every 8th ray of the frame ({len(o[::8])} rays), {dt1:.1f} s"},
-                cpu_model=model, nproc=os.cpu_count(), other_workloads=cpu_other_workloads(threads))
+                cpu_model=model, nproc=os.cpu_count(), other_workloads=cpu_other_workloads(threads, large_kept))
 
 
-def cpu_other_workloads(threads):
+def cpu_other_workloads(threads, large_kept=None):
     """The oracle on the other workloads, on bounded samples: the tiny room in full, the
     batched walk on its first 4 views, the differentiable grid's forward and radiance
-    VJP on 2 of its views."""
+    VJP on 2 of its views, and (when the large leg ran and kept its host data) the two-level
+    city on the central 256x256 pixels of its first view."""
     import numpy as np
     import oracle
     import synth
@@ -155,6 +156,20 @@ def cpu_other_workloads(threads):
             e["vjp_s"] = round(time.perf_counter() - t1, 2)
         out[name] = e
         del g
+    if large_kept:
+        tl, v = large_kept["tl"], large_kept["views"][0]
+        og, cg = oracle.Grid.from_probes(tl.fine), oracle.Grid.from_probes(tl.coarse)
+        o, d = oracle.view_rays(*v.as_tuple())
+        x0, y0 = (v.width - 256) // 2, (v.height - 256) // 2
+        pix = ((y0 + np.arange(256))[:, None] * v.width + x0 + np.arange(256)[None, :]).ravel()
+        o = np.broadcast_to(o, d.shape)[pix] if o.ndim == 1 else o[pix]
+        t0 = time.perf_counter()
+        oracle.trace(og, np.ascontiguousarray(o), np.ascontiguousarray(d[pix]), coarse=(cg, tl.plane_off, tl.ratio),
+                     nthreads=threads)
+        dt = time.perf_counter() - t0
+        out["large_crop"] = {"value": round(len(pix) / dt / 1e6, 4), "unit": "Mrays/s", "rays": len(pix),
+                             "s": round(dt, 2), "sample": "central 256x256 pixels of the first 3840x2160 view"}
+        del og, cg
     return out
 
 
@@ -331,10 +346,11 @@ def paper_maps(pt, synth, torch, np, steps=10):
     return res
 
 
-def large(pt, synth, torch, np, steps=3):
+def large(pt, synth, torch, np, steps=3, keep=None):
     """Two-level city block: fine 64x64x16 + coarse 16x16x4 probes, 128^2 maps (~17 GB of
     probe data in HBM), 8 views of 3840x2160 in one graph-captured persistent launch;
-    forward and forward + backward."""
+    forward and forward + backward.  keep (a dict): receives the host-side hierarchy and
+    views for the oracle's timing on a crop (the cpu leg)."""
     t0 = time.time()
     scene, tl, views = synth.workload("large", nthreads=min(16, os.cpu_count() or 1))
     bake_s = time.time() - t0
@@ -343,6 +359,8 @@ def large(pt, synth, torch, np, steps=3):
     P, N = tl.n_probes, tl.fine.N
     dead = float(np.mean([(ps.distance.reshape(ps.n_probes, -1) == 0).all(1).mean() for ps in (tl.fine, tl.coarse)]))
     n_boxes = len(scene.obj_type)
+    if keep is not None:
+        keep["tl"], keep["views"] = tl, views
     del tl
     va = pt.make_views(views)
     rays = pt.n_rays(views)
@@ -623,12 +641,14 @@ def main():
     if "complexity" in legs:
         print("[bench] scene complexity", file=sys.stderr, flush=True)
         result["complexity"] = complexity(pt, synth, torch, np, opts)
+    large_kept = {} if "cpu" in legs else None
     if "large" in legs:
         print("[bench] large two-level workload", file=sys.stderr, flush=True)
-        result["large"] = large(pt, synth, torch, np)
+        result["large"] = large(pt, synth, torch, np, keep=large_kept)
     if "cpu" in legs:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cb = cpu_baseline(probes, view)
+        cb = cpu_baseline(probes, view, large_kept)
+        large_kept = None
         cb["one_thread"]["value"] = round(cb["one_thread"]["value"], 4)  # other_workloads are rounded already
         result["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(result), flush=True)
