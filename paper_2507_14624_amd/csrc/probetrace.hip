@@ -556,19 +556,9 @@ __device__ __forceinline__ void wave_scatter_add(float *__restrict__ grad, const
     }
 }
 
-// Wavefront-segmented scatter-add through a table in LDS, for texel indices below 2^32 - 1.
-// Every lane holds up to K (texel, C-channel value) contributions (texel = probe N^2 + j N +
-// i, kEmptyTexel for none; the gradient is [texel][C]).  The wave merges them in its own
-// 256-slot table (an entry takes the first free or matching slot from its hash on, linear
-// probing; 256 slots hold the wave's at most 64 K <= 256 distinct texels), compacts the
-// occupied slots in slot order, and issues the C K' sums of its K' texels as ceil(C K' / 64)
-// FP32 atomic instructions with consecutive lanes on consecutive floats.  Against
-// wave_scatter_add, whose loop runs once per distinct texel (a wave sum, then C single-lane
-// atomics), the cost no longer grows with K' in VALU, and a 64-lane atomic instruction over
-// neighbouring texels carried 7x the floats per second of single-lane ones (a probe of both
-// patterns on a 1.6 GB gradient).  The hash keeps the texels of a map row in consecutive
-// slots and spreads neighbouring rows.  All 64 lanes must arrive here together; the table
-// is the wave's alone.
+// A wavefront's table in LDS for merging gradient contributions per texel (the adjoints'
+// scatters below): 256 slots keyed by texel id (probe N^2 + j N + i over both levels;
+// kEmptyTexel marks a free slot), C FP32 channels each.
 constexpr uint32_t kEmptyTexel = 0xffffffffu;
 template <int C>
 struct WaveTableC {
