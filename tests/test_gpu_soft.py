@@ -116,3 +116,57 @@ def test_soft_autograd_function():
     assert torch.allclose(dist.grad, gd, rtol=1e-4, atol=1e-5 * gd.abs().max().item())
     assert torch.allclose(master.grad, gm, rtol=1e-4, atol=1e-5 * gm.abs().max().item())
     assert dist.grad.abs().sum() > 0 and master.grad.abs().sum() > 0
+
+
+def _soft_check(pt, grid, rad, views, og_arg, P, N, sigma, o, d, label, **orc_kw):
+    """Soft colour on the clear rays and both gradients against the oracle (rays in the float
+    margin get no upstream gradient)."""
+    got = pt.probe_trace_soft(grid, rad, views, sigma)
+    orc = oracle.trace_soft(og_arg[0], o, d, sigma, **orc_kw)
+    assert (orc["count"] >= 0).all()
+    clear = orc["margin"] == 0
+    err = np.abs(got.cpu().numpy().astype(np.float64) - orc["rgb"]).max(axis=1)
+    print(f"[soft] {label}: clear {clear.mean():.3f}, mean candidates {orc['count'].mean():.1f}, "
+          f"max err (clear) {err[clear].max():.2e}", flush=True)
+    assert clear.mean() > 0.3
+    assert err[clear].max() <= 1e-3
+    g = np.random.default_rng(12).normal(size=(len(o), 3))
+    g[~clear] = 0.0
+    gd_o, gr_o = oracle.vjp_soft(og_arg, orc, g)
+    gd = torch.zeros((P, N, N), device="cuda")
+    gr = torch.zeros((P, N, N, 3), device="cuda")
+    pt.probe_trace_soft_backward(grid, rad, views, sigma, got, torch.from_numpy(g.astype(np.float32)).cuda(), gd, gr)
+    for what, a, ref in (("distance", gd, gd_o), ("radiance", gr, gr_o)):
+        a = a.cpu().numpy().astype(np.float64)
+        scale = np.abs(ref).max()
+        bound = 3e-3 * np.abs(ref) + 3e-4 * scale
+        err = np.abs(a - ref)
+        print(f"[soft grad] {label} {what}: nonzero {int((ref != 0).sum())}, max err / bound "
+              f"{(err / bound).max():.3f}", flush=True)
+        assert scale > 0
+        assert (err <= bound).all()
+
+
+def test_soft_two_level_city():
+    # the walk visits the coarse cage after the fine one in every cell, and the city's probes
+    # inside buildings (all distances zero) are candidates of weight zero: ~90 per ray
+    pt = _pt()
+    scene, tl, views = workload("large_small")
+    grid = pt.ProbeGrid.from_two_level(tl)
+    rad = torch.from_numpy(tl.radiance().view(np.float16).copy()).cuda()
+    og, cg = oracle.Grid.from_probes(tl.fine), oracle.Grid.from_probes(tl.coarse)
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    _soft_check(pt, grid, rad, views[:1], (og, cg), tl.n_probes, tl.fine.N, 0.25 * 8.0 / tl.fine.N, o, d,
+                "two-level city", coarse=(cg, tl.plane_off, tl.ratio), kcap=1024)
+
+
+def test_soft_fewer_than_8_probes():
+    from test_oracle_few import few_room
+    pt = _pt()
+    scene, probes, views = few_room((2, 2, 1), size=(160, 100))
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    og = oracle.Grid.from_probes(probes)
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    _soft_check(pt, grid, rad, views[:1], (og,), probes.n_probes, probes.N, 0.25 * 8.0 / probes.N, o, d,
+                "2x2x1 probes")
