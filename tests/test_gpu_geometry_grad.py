@@ -53,10 +53,14 @@ def _rays(views):
     return np.concatenate(o_parts), np.concatenate(d_parts)
 
 
-def _check(pt, probes, views, grid, rad, og, use_rgb=True, use_t=True, opts=None, nearest=False):
+def _check(pt, probes, views, grid, rad, og, use_rgb=True, use_t=True, opts=None, nearest=False, coarse=None):
+    """coarse: (coarse oracle grid, plane_off, ratio) of a two-level hierarchy (probes then
+    only gives N; the gradient spans both levels, fine first)."""
     res = {k: v.cpu().numpy() for k, v in pt.probe_trace(grid, rad, views, opts).items()}
     o, d = _rays(views)
-    orc = oracle.trace(og, o, d, nearest=nearest)
+    orc = oracle.trace(og, o, d, nearest=nearest, coarse=coarse)
+    Pf = og.distance.shape[0]
+    position = (lambda p: og.probe_position(p) if p < Pf else coarse[0].probe_position(p - Pf))
     s = compare(res, orc)
     n = s["n"]
     hit = orc["status"] == oracle.HIT
@@ -73,24 +77,25 @@ def _check(pt, probes, views, grid, rad, og, use_rgb=True, use_t=True, opts=None
     if not nearest:
         keep &= ~hit | (np.minimum(np.minimum(fx, 1 - fx), np.minimum(fy, 1 - fy)) > 1e-4)
         pos = np.zeros((n, 3))
-        pos[hit] = np.stack([og.probe_position(p) for p in orc["probe"][hit]])
+        pos[hit] = np.stack([position(p) for p in orc["probe"][hit]])
         q = o + np.where(hit, orc["t"], 0.0)[:, None] * d - pos
         keep &= ~hit | (np.abs(q[:, 2]) > 1e-5 * np.abs(q).sum(1))
     rng = np.random.default_rng(7)
     grgb = rng.normal(size=(n, 3)).astype(np.float32) * keep[:, None] if use_rgb else None
     gt = rng.normal(size=n).astype(np.float32) * keep if use_t else None
-    gg = torch.zeros((probes.n_probes, probes.N, probes.N), dtype=torch.float32, device="cuda")
+    gg = torch.zeros((grid.P_total, probes.N, probes.N), dtype=torch.float32, device="cuda")
     pt.probe_trace_backward_distance(grid, rad, views,
                                      torch.from_numpy(grgb).cuda() if use_rgb else None,
                                      torch.from_numpy(gt).cuda() if use_t else None, gg, opts)
     got = gg.cpu().numpy().astype(np.float64)
     g64 = lambda a: None if a is None else a.astype(np.float64)
-    ref = oracle.vjp_distance(og, orc, grad_rgb=g64(grgb), grad_t=g64(gt))
+    grids = (og, coarse[0]) if coarse else og
+    ref = oracle.vjp_distance(grids, orc, grad_rgb=g64(grgb), grad_t=g64(gt))
     # sum of |contribution| per texel
     absd = dict(orc)
     absd["dtdr"] = np.abs(orc["dtdr"])
     absd["drgbdt"] = np.abs(orc["drgbdt"])
-    mag = oracle.vjp_distance(og, absd, grad_rgb=None if grgb is None else np.abs(g64(grgb)),
+    mag = oracle.vjp_distance(grids, absd, grad_rgb=None if grgb is None else np.abs(g64(grgb)),
                               grad_t=None if gt is None else np.abs(g64(gt)))
     err = np.abs(got - ref)
     tol = 1e-3 * mag + 1e-7
@@ -169,3 +174,18 @@ def test_geometry_autograd_function():
     torch.testing.assert_close(dist.grad, gd, rtol=1e-5, atol=1e-6)
     torch.testing.assert_close(master.grad, gm, rtol=1e-5, atol=1e-6)
     assert torch.count_nonzero(dist.grad).item() > 300
+
+
+def test_distance_adjoint_two_level_hierarchy():
+    # the distance adjoint over both levels of a hierarchy (the city block at reduced size):
+    # hits on coarse probes add into the coarse block of the gradient, after the fine one
+    pt = _pt()
+    scene, tl, views = workload("large_small")
+    rng = np.random.default_rng(3)
+    rads = [rng.uniform(0.0, 1.0, size=(ps.n_probes, ps.N, ps.N, 3)).astype(np.float16) for ps in (tl.fine, tl.coarse)]
+    grid = pt.ProbeGrid.from_two_level(tl)
+    rad = torch.from_numpy(np.concatenate(rads)).cuda()
+    og, cg = (oracle.Grid.from_probes(ps, radiance=r.astype(np.float32)) for ps, r in zip((tl.fine, tl.coarse), rads))
+    got, ref = _check(pt, tl.fine, views, grid, rad, og, coarse=(cg, tl.plane_off, tl.ratio))
+    Pf = tl.fine.n_probes
+    assert np.count_nonzero(ref[:Pf]) > 500 and np.count_nonzero(ref[Pf:]) > 0
