@@ -102,3 +102,30 @@ def test_fp64_degenerate_rays():
     assert valid.all(), np.nonzero(~valid)[0][:10]
     # exact ties are still ties in double: fewer disagree than in FP32, none outside the margin
     assert s["disagree"] <= 0.01 * s["n"]
+
+
+@pytest.mark.parametrize("kw", [dict(nearest=True), dict(thickness_rel=float("inf")), dict(max_probes_per_cell=2),
+                                dict(thickness_rel=0.02, background=(0.25, 0.5, 1.0)),
+                                dict(nearest=True, thickness_rel=float("inf"), max_probes_per_cell=2)],
+                         ids=["nearest", "tau_inf", "two_probes", "tau_bg", "all_literal"])
+def test_fp64_options(kw):
+    # the trace options in double precision: nearest-texel radiance, the classification
+    # without the shadow-entry rule, two cage probes per cell, a thin shell and a background
+    pt = _pt()
+    scene, probes, views = workload("single", size=(240, 135))
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    gkw = {k: v for k, v in kw.items() if k != "nearest"}
+    gkw["flags"] = pt.PT_FLAG_FP64 | (pt.PT_FLAG_NEAREST if kw.get("nearest") else 0)
+    r64 = _np(pt.probe_trace(grid, rad, views[:1], pt.trace_opts(**gkw)))
+    orc = oracle.trace_view(oracle.Grid.from_probes(probes), views[0].as_tuple(), **kw)
+    s = compare(r64, orc)
+    assert_parity(s, f"FP64 {kw}")
+    assert s["disagree"] <= 1
+    if kw.get("nearest"):
+        h = r64["status"] == oracle.HIT
+        R = probes.radiance.view(np.float16).astype(np.float32).reshape(probes.n_probes, -1, 3)
+        assert np.array_equal(r64["rgb"][h], R[r64["hit"][h, 0], r64["hit"][h, 1]])
+    if "background" in kw:
+        miss = r64["status"] != oracle.HIT
+        assert miss.any() and np.all(r64["rgb"][miss] == np.float32(kw["background"]))
