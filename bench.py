@@ -357,7 +357,7 @@ def large(pt, synth, torch, np, steps=3, keep=None):
     grid = pt.ProbeGrid.from_two_level(tl)
     rad = torch.from_numpy(tl.radiance().view(np.float16)).cuda()
     P, N = tl.n_probes, tl.fine.N
-    dead = float(np.mean([(ps.distance.reshape(ps.n_probes, -1) == 0).all(1).mean() for ps in (tl.fine, tl.coarse)]))
+    solid = [float((ps.distance.reshape(ps.n_probes, -1) <= 0).all(1).mean()) for ps in (tl.fine, tl.coarse)]
     n_boxes = len(scene.obj_type)
     if keep is not None:
         keep["tl"], keep["views"] = tl, views
@@ -406,8 +406,8 @@ def large(pt, synth, torch, np, steps=3, keep=None):
         roof = {"forward": hbm_roof(ab["total_bytes"], ms, "k_trace_persistent<true, 1>"),
                 "bytes_per_ray": round(ab["bytes_per_ray"], 2), "sample": ab.get("sample")}
     return {"workload": f"city block of {n_boxes} boxes; fine 64x64x16 + coarse 16x16x4 probes (coarse planes = every "
-                        f"4th fine plane), 128^2 maps, 5-level pyramids, {P} probes ({dead:.0%} inside buildings, "
-                        f"D = 0); 8 views of 3840x2160", "rays": rays, "hbm_probe_bytes": int(P * N * N * (8 + 4 + 6)),
+                        f"4th fine plane), 128^2 maps, 5-level pyramids, {P} probes ({solid[0]:.0%} of the fine and "
+                        f"{solid[1]:.0%} of the coarse inside buildings, D = 0); 8 views of 3840x2160", "rays": rays, "hbm_probe_bytes": int(P * N * N * (8 + 4 + 6)),
             "host_bake_s": round(bake_s, 1), "hit_frac": round(hit_frac, 4),
             "fwd": {"value": round(rays / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms": round(ms, 3),
                     "launch": "one graph-captured persistent launch over the 8 views"},

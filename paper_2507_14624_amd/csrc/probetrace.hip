@@ -91,6 +91,7 @@ struct pt_grid {
     int64_t stride = 0;
     float *pyr = nullptr;
     uint32_t *nrm = nullptr;
+    uint8_t *solid = nullptr;  // [P] 1 for a probe whose stored distances are all <= 0
     // multi-view launches: view table and tile counter
     ViewDev *views_dev = nullptr;
     ViewDev *views_host = nullptr;  // pinned staging
@@ -139,6 +140,19 @@ __global__ void k_mip(float *__restrict__ pyr, int N, int l, int64_t stride, int
     float a = c[(2 * j) * N + 2 * i], b = c[(2 * j) * N + 2 * i + 1];
     float d = c[(2 * j + 1) * N + 2 * i], e = c[(2 * j + 1) * N + 2 * i + 1];
     blk[level_offset(N, l) + j * N + i] = fminf(fminf(a, b), fminf(d, e));
+}
+
+// Probes inside solids: every stored distance of the probe is <= 0 (not NaN), so every
+// trace of such a probe fires at the first texel of its first piece behind the stored
+// surface and answers UNKNOWN (unless the eye sits on the probe; see k_cage_order).  One
+// workgroup per probe over its level-0 map.
+__global__ void __launch_bounds__(256) k_probe_solid(const float *__restrict__ pyr, int64_t stride, int NN,
+                                                     uint8_t *__restrict__ solid) {
+    const float *d = pyr + (int64_t)blockIdx.x * stride;
+    int ok = 1;
+    for (int i = threadIdx.x; i < NN; i += 256) ok &= d[i] <= 0.0f ? 1 : 0;
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) solid[blockIdx.x] = (uint8_t)ok;
 }
 
 __global__ void k_read_level(const float *__restrict__ pyr, float *__restrict__ out, int N, int l, int64_t stride,
@@ -221,6 +235,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: pyramid allocation");
     if (hipMalloc(&g->nrm, (size_t)(P * N * N) * sizeof(uint32_t)) != hipSuccess)
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: normal allocation");
+    if (hipMalloc(&g->solid, (size_t)P) != hipSuccess)
+        return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: probe flag allocation");
     if (hipMalloc(&g->counter, 64) != hipSuccess) return cleanup(PT_ERR_OUT_OF_MEMORY, "counter allocation");
     if (hipEventCreateWithFlags(&g->staging_free, hipEventDisableTiming) != hipSuccess)
         return cleanup(PT_ERR_HIP, "hipEventCreate failed");
@@ -231,6 +247,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         int64_t tl = P * (int64_t)(N >> l) * (N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, N, l, g->stride, tl);
     }
+    hipLaunchKernelGGL(k_probe_solid, dim3((unsigned)P), dim3(256), 0, s, g->pyr, g->stride, N * N, g->solid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(PT_ERR_HIP, std::string("probe_grid_create launch: ") + hipGetErrorString(e));
     *out = g;
@@ -250,6 +267,7 @@ extern "C" void probe_grid_destroy(pt_grid *g) {
     if (g->graph.capture) (void)hipStreamDestroy(g->graph.capture);
     if (g->pyr) (void)hipFree(g->pyr);
     if (g->nrm) (void)hipFree(g->nrm);
+    if (g->solid) (void)hipFree(g->solid);
     if (g->counter) (void)hipFree(g->counter);
     if (g->views_dev) (void)hipFree(g->views_dev);
     if (g->views_host) (void)hipHostFree(g->views_host);
@@ -331,16 +349,47 @@ __device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *_
 }
 
 
-// Cage order of every cell for every view (the eye is the same for all rays of a view).
+// Cage word of every cell for every view (the eye is the same for all rays of a view): the
+// cage order, limited to its first max_probes codes.  With `solid` flags, the probes inside
+// solids are left out of the word and its solid bit set instead: such a probe answers
+// UNKNOWN wherever the walk reaches it, so the walk's first HIT in cage order is the same
+// without it, and for a ray that hits nothing the bit marks the UNKNOWN it would have
+// given (every rank of the cell is reached then).  A probe the eye sits on (within the eye
+// radius, tested exactly as the trace tests it) stays: its eye lookup may be a HIT at t = 0.
+// One case differs: a segment that lies wholly within 2^-12 of the position scale of a
+// solid probe's centre, which the trace trims to nothing (MISS); left out, the probe counts
+// as UNKNOWN, the answer of the exact method.
 __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single, int n_views, int cells,
-                             uint32_t *__restrict__ tab) {
+                             const uint8_t *__restrict__ solid, uint32_t *__restrict__ tab) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_views * cells) return;
     int v = (int)(i / cells), c = (int)(i % cells);
     const float *X = views ? views[v].pos : single.pos;
     int nx = g.cmax[0] + 1, ny = g.cmax[1] + 1;
     int cell[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
-    tab[i] = g.few ? cage_order<true>(g, cell, X) : cage_order<false>(g, cell, X);
+    const uint32_t order = g.few ? cage_order<true>(g, cell, X) : cage_order<false>(g, cell, X);
+    if (!solid) {
+        tab[i] = cage_word(order, g.max_probes);
+        return;
+    }
+    uint32_t kept = 0, flag = 0;
+    int n = 0;
+    for (int rk = 0; rk < g.max_probes; ++rk) {
+        const int code = (int)((order >> (3 * rk)) & 7u);
+        int pc[3];
+        cage_probe(g, g.few != 0, cell, code, pc);
+        const int p = pc[0] + g.n[0] * (pc[1] + g.n[1] * pc[2]);
+        float Xp[3];
+        for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord<float>(g, a, pc[a]);
+        const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
+        if (solid[p] && !(d2 <= g.eye_eps2)) {
+            flag = kCageSolid;
+        } else {
+            kept |= (uint32_t)code << (3 * n);
+            ++n;
+        }
+    }
+    tab[i] = cage_word(kept, n) | flag;
 }
 
 // Kernel template parameters: W = 64-bit probe addressing, T = layout (kGrid, kTwoLevel:
@@ -1061,6 +1110,8 @@ struct TraceCtx {
     Level2 L2;     // coarse level (two == true)
     bool wide, two;
     int ccells;    // coarse cells
+    // per-probe solid flags of both levels, or null: the cage tables then list every probe
+    const uint8_t *solid, *csolid;
 };
 
 static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
@@ -1068,6 +1119,8 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
     make_griddev(g, opts, c.d);
     c.two = g->coarse != nullptr;
     c.wide = g->wide || (opts && (opts->flags & PT_FLAG_WIDE));
+    const bool skip = !(opts && (opts->flags & PT_FLAG_TRACE_SOLID_PROBES));
+    c.solid = skip ? g->solid : nullptr;
     if (c.two) {
         make_griddev(g->coarse, opts, c.L2.c);
         for (int a = 0; a < 3; ++a) {
@@ -1076,6 +1129,7 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
         }
         c.L2.Pf = g->P;
         c.wide = c.wide || g->coarse->wide;
+        c.csolid = skip ? g->coarse->solid : nullptr;
         c.ccells = g->coarse->cells;
     }
 }
@@ -1100,11 +1154,11 @@ static void launch_cage_tables(const pt_grid *g, const TraceCtx &c, const ViewDe
                                int n_views, uint32_t *cage, uint32_t *ccage, hipStream_t s) {
     int64_t nc = (int64_t)n_views * g->cells;
     hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, c.d, views_dev, one, n_views,
-                       g->cells, cage);
+                       g->cells, c.solid, cage);
     if (c.two) {
         int64_t ncc = (int64_t)n_views * c.ccells;
         hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(ncc, 256)), dim3(256), 0, s, c.L2.c, views_dev, one,
-                           n_views, c.ccells, ccage);
+                           n_views, c.ccells, c.csolid, ccage);
     }
 }
 
@@ -1576,6 +1630,9 @@ static pt_status launch_soft(const pt_grid *g, const pt_view *views_host, int32_
     }
     st = upload_views(mg, vd, s);
     if (st != PT_OK) return st;
+    // a probe inside a solid can still give a candidate (its first firing texel may face
+    // the ray): the soft walk traces every probe
+    c.solid = c.csolid = nullptr;
     launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, mg->counter);
 #define PT_LAUNCH(W, T)                                                                                       \
@@ -1732,6 +1789,7 @@ extern "C" pt_status probe_grid_set_distance(pt_grid *g, const float *distance_d
         int64_t tl = (int64_t)g->P * (int64_t)(g->N >> l) * (g->N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, g->N, l, g->stride, tl);
     }
+    hipLaunchKernelGGL(k_probe_solid, dim3((unsigned)g->P), dim3(256), 0, s, g->pyr, g->stride, g->N * g->N, g->solid);
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }

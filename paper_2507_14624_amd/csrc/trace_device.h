@@ -631,6 +631,14 @@ __device__ __forceinline__ uint32_t cage_order(const GridDev &g, const int cell[
     return packed;
 }
 
+// A cell's cage word: bits 0-23 the corner codes to trace, closest to the eye first (3 bits
+// each), bits 24-27 how many, bit 28 set when codes among the first max_probes were left
+// out because their probes sit inside solids (see k_cage_order).
+constexpr uint32_t kCageSolid = 1u << 28;
+__device__ __forceinline__ uint32_t cage_word(uint32_t codes, int ranks) {
+    return (codes & 0xffffffu) | ((uint32_t)ranks << 24);
+}
+
 __device__ __forceinline__ int cell_index(const GridDev &g, const int cell[3]) {
     return cell[0] + (g.cmax[0] + 1) * (cell[1] + (g.cmax[1] + 1) * cell[2]);
 }
@@ -752,18 +760,22 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const R X[3], cons
             tn[a] = pidx >= 0 ? plane_t(grid_coord<R>(g, a, pidx), X[a], iw[a]) : R(INFINITY);
         }
         R tb = fmin(fmin(fmin(tn[0], tn[1]), tn[2]), tfar);
-        uint32_t order = cage ? cage[cell_index(g, cell)] : cage_order<Few>(g, cell, X);
+        uint32_t order = cage ? cage[cell_index(g, cell)] : cage_word(cage_order<Few>(g, cell, X), g.max_probes);
         int ccell[3] = {0, 0, 0};
         uint32_t corder = 0;
         if (Two) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 ccell[a] = min(max(floor_div(cell[a] - L2.off[a], L2.ratio[a]), 0), L2.c.cmax[a]);
-            corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_order<false>(L2.c, ccell, X);
+            corder = ccage ? ccage[cell_index(L2.c, ccell)] : cage_word(cage_order<false>(L2.c, ccell, X), L2.c.max_probes);
         }
         // the cage of one level, closest to the eye first; true on a HIT
         auto cage_walk = [&](const GridDev &G, const int cl[3], uint32_t ord, int lev) -> bool {
-            for (int rk = 0; rk < G.max_probes; ++rk) {
+            // probes left out of the word were inside solids: each would have answered
+            // UNKNOWN, which only matters for a ray that hits nothing at all
+            if (ord & kCageSolid) any_unknown = true;
+            const int ranks = (int)((ord >> 24) & 15u);
+            for (int rk = 0; rk < ranks; ++rk) {
                 int c = (int)(ord & 7u);
                 ord >>= 3;
                 ProbeResult<R> pr;

@@ -75,3 +75,15 @@ def test_host_side_argument_errors():
                                      (8, 1, 1e-3, 0.9, 1.5, 1e-8), (8, 1, 1e-3, 0.9, 0.999, float("inf"))):
         assert lib.pt_adam_step(dummy, dummy, dummy, dummy, None, n, step, lr, b1, b2, eps, 0.0, None) == 1
     lib.probe_grid_destroy(None)  # ignored
+
+
+def test_binding_flags_match_the_header():
+    # every PT_FLAG_* of the header has the same value in the Python binding, and no two
+    # flags share a bit
+    import paper_2507_14624_amd as pt
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define (PT_FLAG_\w+) (\d+)u", open(HEADER).read()))
+    assert len(flags) >= 9
+    for k, v in flags.items():
+        assert getattr(pt, k) == v, k
+        assert v & (v - 1) == 0, k
+    assert len(set(flags.values())) == len(flags)
