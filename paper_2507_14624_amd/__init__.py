@@ -27,7 +27,7 @@ PT_FLAG_START_TEXEL = 16
 PT_FLAG_NO_START_TEXEL = 32
 PT_FLAG_FP64 = 64
 PT_FLAG_SCATTER_PER_TEXEL = 128
-PT_FLAG_TRACE_SOLID_PROBES = 256
+PT_FLAG_TRACE_ALL_PROBES = 256
 
 EXPORTED = ("pt_trace_opts_default", "probe_grid_create", "probe_grid_destroy", "probe_grid_read_level",
             "probe_grid_set_coarse", "probe_grid_set_distance", "probe_bake_points",

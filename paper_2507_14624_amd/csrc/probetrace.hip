@@ -349,18 +349,51 @@ __device__ __forceinline__ void write_result(const GridDev &g, const uint16_t *_
 }
 
 
+// In the eye's cell every ray's first piece starts at the eye, and its octant is the
+// eye's own as seen from the probe (the piece ends at the first sign change of X - O +
+// t w).  So its start texel, the radial distance there and whether that texel fires
+// behind the stored surface are the same for every ray of the view: when they are, with
+// the start-texel test on, the probe answers UNKNOWN for every ray that reaches it.  The
+// same expressions as the trace (piece_setup, piece_xy, rho2_at at t = 0, where the
+// direction drops out) give the same bits.  Left undecided: an eye within 10^-3 spacings of
+// one of the probe's axis planes (the octant of a ray's first piece could then round
+// either way), and an eye close enough to the probe for the trace to trim the piece's
+// start (L below 2^-11 of the position scale for the farthest segment end).
+__device__ bool eye_start_unknown(const GridDev &g, int p, const float Xp[3], float tbmax) {
+    const float sp = fminf(g.spc[0], fminf(g.spc[1], g.spc[2]));
+    for (int a = 0; a < 3; ++a)
+        if (!(fabsf(Xp[a]) >= 1e-3f * sp)) return false;
+    const float still[3] = {0.0f, 0.0f, 0.0f};
+    Piece<float> s;
+    piece_setup(s, Xp, still, 0.0f, 1.0f, g.N);
+    float xs, ys, Ls;
+    piece_xy(s, Xp, still, 0.0f, g.N, xs, ys, Ls);
+    const float thr = (((fabsf(Xp[0]) + fabsf(Xp[1])) + fabsf(Xp[2])) + 2.0f * tbmax) * 0x1p-12f;
+    if (!(Ls >= 2.0f * thr)) return false;
+    const int i0 = min(max((int)floor(xs), s.ilo), s.ihi);
+    const int j0 = min(max((int)floor(ys), s.jlo), s.jhi);
+    const float rs2 = rho2_at(Xp, still, 0.0f);
+    const float r = g.pyr[(int64_t)p * g.stride + ((int64_t)j0 << g.logN) + i0];
+    if (!below(r, rs2)) return false;
+    const float t1 = r * g.tau1;
+    return (t1 < 0.0f) || (rs2 > t1 * t1);
+}
+
 // Cage word of every cell for every view (the eye is the same for all rays of a view): the
-// cage order, limited to its first max_probes codes.  With `solid` flags, the probes inside
-// solids are left out of the word and its solid bit set instead: such a probe answers
-// UNKNOWN wherever the walk reaches it, so the walk's first HIT in cage order is the same
-// without it, and for a ray that hits nothing the bit marks the UNKNOWN it would have
-// given (every rank of the cell is reached then).  A probe the eye sits on (within the eye
-// radius, tested exactly as the trace tests it) stays: its eye lookup may be a HIT at t = 0.
-// One case differs: a segment that lies wholly within 2^-12 of the position scale of a
-// solid probe's centre, which the trace trims to nothing (MISS); left out, the probe counts
-// as UNKNOWN, the answer of the exact method.
+// cage order, limited to its first max_probes codes.  With `solid` flags (skip enabled),
+// the probes known to answer UNKNOWN for every ray of the view that reaches them are left
+// out of the word and its UNKNOWN bit set instead: the walk's first HIT in cage order is the
+// same without them, and for a ray that hits nothing the bit marks the UNKNOWN they would
+// have given (every rank of the cell is reached then).  Those probes are the ones inside
+// solids (a stored distance <= 0 fires on any piece's first texel, behind the surface) and,
+// when `eye_cell` is set (the level whose cells are the walk's own), the probes of the
+// eye's cell whose start texel fires behind the surface (eye_start_unknown).  A probe the
+// eye sits on (within the eye radius, tested exactly as the trace tests it) stays: its eye
+// lookup may be a HIT at t = 0.  One case differs from tracing a solid probe: a segment
+// wholly within 2^-12 of the position scale of its centre, which the trace trims to nothing
+// (MISS) and the word counts UNKNOWN, the exact method's answer.
 __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single, int n_views, int cells,
-                             const uint8_t *__restrict__ solid, uint32_t *__restrict__ tab) {
+                             const uint8_t *__restrict__ solid, int eye_cell, uint32_t *__restrict__ tab) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_views * cells) return;
     int v = (int)(i / cells), c = (int)(i % cells);
@@ -372,6 +405,22 @@ __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewD
         tab[i] = cage_word(order, g.max_probes);
         return;
     }
+    // the eye's cell, as the walk finds it, and the farthest any segment end can be from the
+    // eye (the scene box exit, which the walk stretches by 1e-4)
+    bool at_eye = eye_cell != 0 && g.start_test != 0;
+    float tbmax = 0.0f;
+    if (at_eye) {
+        for (int a = 0; a < 3; ++a) {
+            const float q = (X[a] - g.org[a]) * g.ispc[a];
+            at_eye = at_eye && cell[a] == min(max((int)floor(q), 0), g.cmax[a]);
+        }
+        float far2 = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            const float e = fmaxf(fabsf(g.smin[a] - X[a]), fabsf(g.smax[a] - X[a]));
+            far2 += e * e;
+        }
+        tbmax = sqrtf(far2) * 1.001f + 1e-3f;
+    }
     uint32_t kept = 0, flag = 0;
     int n = 0;
     for (int rk = 0; rk < g.max_probes; ++rk) {
@@ -382,8 +431,9 @@ __global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewD
         float Xp[3];
         for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord<float>(g, a, pc[a]);
         const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
-        if (solid[p] && !(d2 <= g.eye_eps2)) {
-            flag = kCageSolid;
+        const bool eye_on = d2 <= g.eye_eps2;
+        if (!eye_on && (solid[p] || (at_eye && eye_start_unknown(g, p, Xp, tbmax)))) {
+            flag = kCageUnknown;
         } else {
             kept |= (uint32_t)code << (3 * n);
             ++n;
@@ -1119,7 +1169,7 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
     make_griddev(g, opts, c.d);
     c.two = g->coarse != nullptr;
     c.wide = g->wide || (opts && (opts->flags & PT_FLAG_WIDE));
-    const bool skip = !(opts && (opts->flags & PT_FLAG_TRACE_SOLID_PROBES));
+    const bool skip = !(opts && (opts->flags & PT_FLAG_TRACE_ALL_PROBES));
     c.solid = skip ? g->solid : nullptr;
     if (c.two) {
         make_griddev(g->coarse, opts, c.L2.c);
@@ -1154,11 +1204,11 @@ static void launch_cage_tables(const pt_grid *g, const TraceCtx &c, const ViewDe
                                int n_views, uint32_t *cage, uint32_t *ccage, hipStream_t s) {
     int64_t nc = (int64_t)n_views * g->cells;
     hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, c.d, views_dev, one, n_views,
-                       g->cells, c.solid, cage);
+                       g->cells, c.solid, 1, cage);
     if (c.two) {
         int64_t ncc = (int64_t)n_views * c.ccells;
         hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(ncc, 256)), dim3(256), 0, s, c.L2.c, views_dev, one,
-                           n_views, c.ccells, c.csolid, ccage);
+                           n_views, c.ccells, c.csolid, 0, ccage);
     }
 }
 

@@ -1,10 +1,13 @@
-"""Probes inside solids (every stored distance <= 0) on the GPU.  The hard walk's per-view
-cage tables leave them out, since each would answer UNKNOWN wherever the walk reached it;
-PT_FLAG_TRACE_SOLID_PROBES traces them.  Checked here: the same outputs bit for bit either
-way on the city block, where most probes of both levels sit inside buildings, in every
-launch form and in the adjoints; a probe the eye sits on is still traced (its eye lookup is
-a HIT at t = 0); the flags follow probe_grid_set_distance (zeroed, negative and NaN maps);
-and a layout of fewer than 8 probes.  Each default result is also held to the oracle."""
+"""Probes the per-view cage tables leave out of the hard walk, because they answer UNKNOWN
+for every ray of the view that reaches them (PT_FLAG_TRACE_ALL_PROBES traces them):
+probes inside solids (every stored distance <= 0) and, in the eye's cell, probes whose
+first texel fires behind the stored surface for the eye itself.  Checked here: the same
+outputs bit for bit either way on the city block, where most probes of both levels sit
+inside buildings, in every launch form and in the adjoints; on the room, the 64-view walk
+and the paper's 2048^2 maps, where the eye's cell gives such probes; a probe the eye sits
+on is still traced (its eye lookup is a HIT at t = 0); the flags follow
+probe_grid_set_distance (zeroed, negative and NaN maps); and a layout of fewer than 8
+probes.  Each default result is also held to the oracle."""
 import dataclasses
 
 import numpy as np
@@ -65,11 +68,11 @@ def test_city_skip_gives_identical_results_in_every_launch_form():
     ref = _np(pt.probe_trace(grid, rad, views))
     assert_parity(compare(ref, _oracle_views(tl, og, cg, views)), "city, solid probes left out")
     for flags in (0, pt.PT_FLAG_PERSISTENT, pt.PT_FLAG_GRAPH, pt.PT_FLAG_WIDE):
-        for extra in (0, pt.PT_FLAG_TRACE_SOLID_PROBES):
+        for extra in (0, pt.PT_FLAG_TRACE_ALL_PROBES):
             got = _np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags | extra)))
             _same(got, ref, (flags, extra))
     rays = sum(v.width * v.height for v in views)
-    for extra in (0, pt.PT_FLAG_TRACE_SOLID_PROBES):
+    for extra in (0, pt.PT_FLAG_TRACE_ALL_PROBES):
         out = (torch.empty((rays, 3), device="cuda"), torch.empty(rays, device="cuda"),
                torch.empty(rays, dtype=torch.uint8, device="cuda"), torch.empty((rays, 2), dtype=torch.int32,
                                                                                   device="cuda"))
@@ -90,7 +93,7 @@ def test_city_adjoints_with_and_without_the_skip():
     gt = torch.from_numpy(np.random.default_rng(4).normal(size=rays).astype(np.float32)).cuda()
     P, N = tl.n_probes, tl.fine.N
     out = {}
-    for extra in (0, pt.PT_FLAG_TRACE_SOLID_PROBES):
+    for extra in (0, pt.PT_FLAG_TRACE_ALL_PROBES):
         for pers in (0, pt.PT_FLAG_PERSISTENT):
             opts = pt.trace_opts(flags=extra | pers)
             gr = torch.zeros((P, N, N, 3), device="cuda")
@@ -121,7 +124,7 @@ def test_eye_on_a_solid_probe_keeps_its_eye_lookup():
     pos = og.probe_position(p).astype(np.float32).astype(np.float64)
     v = dataclasses.replace(views[0], pos=pos, width=64, height=48)
     a = _np(pt.probe_trace(grid, rad, [v]))
-    b = _np(pt.probe_trace(grid, rad, [v], pt.trace_opts(flags=pt.PT_FLAG_TRACE_SOLID_PROBES)))
+    b = _np(pt.probe_trace(grid, rad, [v], pt.trace_opts(flags=pt.PT_FLAG_TRACE_ALL_PROBES)))
     _same(a, b, "eye on a solid probe")
     assert np.all(a["status"] == oracle.HIT) and np.all(a["t"] == 0.0) and np.all(a["hit"][:, 0] == p)
     assert_parity(compare(a, _oracle_views(tl, og, cg, [v])), "eye on a solid probe")
@@ -147,7 +150,7 @@ def test_flags_follow_set_distance():
                          torch.from_numpy(probes.normal.view(np.float16)).cuda())
     a = _np(pt.probe_trace(grid, rad, views[:1]))
     _same(a, _np(pt.probe_trace(fresh, rad, views[:1])), "set_distance vs fresh grid")
-    _same(a, _np(pt.probe_trace(grid, rad, views[:1], pt.trace_opts(flags=pt.PT_FLAG_TRACE_SOLID_PROBES))),
+    _same(a, _np(pt.probe_trace(grid, rad, views[:1], pt.trace_opts(flags=pt.PT_FLAG_TRACE_ALL_PROBES))),
           "set_distance, solid probes traced")
     og = oracle.Grid(probes.dims, probes.origin, probes.spacing, N, probes.levels, probes.scene_min, probes.scene_max,
                      d2, probes.normal, rad16.astype(np.float32))
@@ -172,9 +175,42 @@ def test_fewer_than_8_probes_with_a_solid_probe():
                         probes.scene_max, torch.from_numpy(d2).cuda(),
                         torch.from_numpy(probes.normal.view(np.float16)).cuda())
     a = _np(pt.probe_trace(grid, rad, views))
-    for flags in (pt.PT_FLAG_TRACE_SOLID_PROBES, pt.PT_FLAG_PERSISTENT):
+    for flags in (pt.PT_FLAG_TRACE_ALL_PROBES, pt.PT_FLAG_PERSISTENT):
         _same(a, _np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags))), ("few", flags))
     og = oracle.Grid(probes.dims, probes.origin, probes.spacing, probes.N, probes.levels, probes.scene_min,
                      probes.scene_max, d2, probes.normal, rad16.astype(np.float32))
     assert_parity(compare(a, oracle.trace_view(og, views[0].as_tuple())), "few (2,2,1), probe 1 solid")
     assert np.all(a["hit"][a["status"] == oracle.HIT, 0] != 1)
+
+
+@pytest.mark.parametrize("name,kw,nviews", [("single", dict(size=(480, 270)), 1), ("batched", {}, 6),
+                                            ("paper", dict(size=(480, 270)), 1)])
+def test_eye_cell_skip_gives_identical_results(name, kw, nviews):
+    # every ray starts in the eye's cell, where the start texel of each cage probe is the
+    # same for the whole view: probes whose start texel fires behind the surface are left
+    # out; the outputs must be those of tracing them
+    pt = _pt()
+    scene, probes, views = workload(name, **kw)
+    views = views[:nviews]
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad16 = probes.radiance.view(np.float16)
+    rad = torch.from_numpy(rad16.copy()).cuda()
+    ref = _np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=pt.PT_FLAG_TRACE_ALL_PROBES)))
+    for flags in (0, pt.PT_FLAG_PERSISTENT, pt.PT_FLAG_GRAPH):
+        _same(_np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags))), ref, (name, flags))
+    if nviews == 1 and name == "single":
+        og = oracle.Grid.from_probes(probes)
+        assert_parity(compare(ref, oracle.trace_view(og, views[0].as_tuple())), f"{name} eye-cell skip")
+    # the recomputing adjoint walks the same tables: the same sums up to the order of the
+    # FP32 additions, bounded by the sum of the contributions' magnitudes (the adjoint of |g|)
+    rays = sum(v.width * v.height for v in views)
+    g = torch.from_numpy(np.random.default_rng(5).normal(size=(rays, 3)).astype(np.float32)).cuda()
+    grads = []
+    for flags, gg in ((0, g), (pt.PT_FLAG_TRACE_ALL_PROBES, g), (pt.PT_FLAG_TRACE_ALL_PROBES, g.abs())):
+        gr = torch.zeros((probes.n_probes, probes.N, probes.N, 3), device="cuda")
+        pt.probe_trace_backward(grid, views, gg, gr, pt.trace_opts(flags=flags | pt.PT_FLAG_PERSISTENT))
+        grads.append(gr.cpu().numpy().astype(np.float64))
+    err = np.abs(grads[0] - grads[1])
+    assert (err <= 1e-5 * grads[2] + 1e-7).all(), (err / (grads[2] + 1e-7)).max()
+    assert np.array_equal(grads[0] != 0, grads[1] != 0)
+    assert np.count_nonzero(grads[1]) > 1000
