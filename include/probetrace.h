@@ -138,21 +138,25 @@ typedef struct {
                                           Same sums up to FP32 summation order */
 #define PT_FLAG_TRACE_ALL_PROBES 256u /* trace every cage probe.  By default the per-view
                                          cage tables of the hard walk leave out the probes
-                                         that answer UNKNOWN for every ray of the view that
-                                         reaches them: probes inside solids (every stored
-                                         distance <= 0, flagged whenever the distances are
-                                         set) and, in the eye's cell with the start-texel
-                                         test on, probes whose first texel, the same for all
-                                         rays there, fires behind the stored surface.  The
-                                         first HIT is the same, and a ray that hits nothing
-                                         is still UNKNOWN.  A probe the eye sits on is always
-                                         traced (its eye lookup may HIT), and so is every
-                                         probe of the walks that sort cages per ray (FP64,
-                                         probe_trace_rays) and of the soft walk.  The one
-                                         case that differs: a segment wholly within 2^-12
-                                         of the position scale of a solid probe, which the
-                                         trace trims to nothing (MISS) and the skip counts
-                                         as UNKNOWN, as the exact method does */
+                                         whose answer is known for every ray of the view that
+                                         reaches them.  UNKNOWN: probes inside solids (every
+                                         stored distance <= 0) and, in the eye's cell with the
+                                         start-texel test on, probes whose first texel, the
+                                         same for all rays there, fires behind the stored
+                                         surface.  MISS: probes whose nearest stored surface,
+                                         over every octant a ray piece in the cell can take,
+                                         lies beyond the cell's farthest point (per-probe
+                                         octant minima, set with the distances).  The first
+                                         HIT is the same, and a ray that hits nothing is
+                                         still UNKNOWN or MISS.  A probe the eye sits on is
+                                         always traced (its eye lookup may HIT), and so is
+                                         every probe of the coarse level of a hierarchy (MISS
+                                         part), of the walks that sort cages per ray (FP64,
+                                         probe_trace_rays) and of the soft walk.  The one case
+                                         that differs: a segment wholly within 2^-12 of the
+                                         position scale of a solid probe, which the trace
+                                         trims to nothing (MISS) and the skip counts as
+                                         UNKNOWN, as the exact method does */
 
 void pt_trace_opts_default(pt_trace_opts *opts);
 

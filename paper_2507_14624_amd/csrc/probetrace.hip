@@ -92,6 +92,7 @@ struct pt_grid {
     float *pyr = nullptr;
     uint32_t *nrm = nullptr;
     uint8_t *solid = nullptr;  // [P] 1 for a probe whose stored distances are all <= 0
+    float *octmin = nullptr;   // [P][8] smallest stored distance per octant (k_probe_flags)
     // multi-view launches: view table and tile counter
     ViewDev *views_dev = nullptr;
     ViewDev *views_host = nullptr;  // pinned staging
@@ -142,16 +143,51 @@ __global__ void k_mip(float *__restrict__ pyr, int N, int l, int64_t stride, int
     blk[level_offset(N, l) + j * N + i] = fminf(fminf(a, b), fminf(d, e));
 }
 
-// Probes inside solids: every stored distance of the probe is <= 0 (not NaN), so every
-// trace of such a probe fires at the first texel of its first piece behind the stored
-// surface and answers UNKNOWN (unless the eye sits on the probe; see k_cage_order).  One
-// workgroup per probe over its level-0 map.
-__global__ void __launch_bounds__(256) k_probe_solid(const float *__restrict__ pyr, int64_t stride, int NN,
-                                                     uint8_t *__restrict__ solid) {
+// Per-probe facts the per-view cage tables use (k_cage_order), from the level-0 map; one
+// workgroup per probe.
+// * solid: every stored distance is <= 0 (none NaN), so every trace of the probe fires at
+//   the first texel of its first piece, behind the stored surface, and answers UNKNOWN
+//   (unless the eye sits on the probe).
+// * octmin[o], o = [x >= 0] + 2 [y >= 0] + 4 [z >= 0]: the smallest stored distance (NaN,
+//   which never fires, left out) over the texels a ray piece in that octant can reach: the
+//   octant's triangle of its quadrant (the inner diamond for z >= 0, the outer corners for
+//   z < 0), widened by a texel band across the fold diagonal, and the texels of the
+//   neighbouring quadrants next to the quadrant's edges (a piece lying within rounding of
+//   one of the probe's axis planes may take the octant across it, and then reaches only
+//   those).  In texel units from the quadrant's centre corner a texel spans a..a+1 and
+//   b..b+1, and the fold is a + b = N/2.
+__global__ void __launch_bounds__(256) k_probe_flags(const float *__restrict__ pyr, int64_t stride, int N,
+                                                     uint8_t *__restrict__ solid, float *__restrict__ octmin) {
+    __shared__ float red[8][256];
     const float *d = pyr + (int64_t)blockIdx.x * stride;
+    const int h = N >> 1, NN = N * N;
     int ok = 1;
-    for (int i = threadIdx.x; i < NN; i += 256) ok &= d[i] <= 0.0f ? 1 : 0;
+    float m[8];
+    for (int o = 0; o < 8; ++o) m[o] = INFINITY;
+    for (int k = threadIdx.x; k < NN; k += 256) {
+        const float x = d[k];
+        ok &= x <= 0.0f ? 1 : 0;
+        if (!(x == x)) continue;
+        const int i = k & (N - 1), j = k / N;
+        const int sx = i >= h, sy = j >= h;
+        const int a = sx ? i - h : h - 1 - i, b = sy ? j - h : h - 1 - j;
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const bool own = ox == sx && oy == sy;
+            const bool edge = (ox == sx || a == 0) && (oy == sy || b == 0);
+            const bool tri = oz ? a + b <= h + 1 : a + b >= h - 3;
+            if ((own && tri) || (!own && edge)) m[o] = fminf(m[o], x);
+        }
+    }
     ok = __syncthreads_and(ok);
+    for (int o = 0; o < 8; ++o) red[o][threadIdx.x] = m[o];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int o = 0; o < 8; ++o) red[o][threadIdx.x] = fminf(red[o][threadIdx.x], red[o][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) octmin[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
     if (threadIdx.x == 0) solid[blockIdx.x] = (uint8_t)ok;
 }
 
@@ -235,7 +271,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: pyramid allocation");
     if (hipMalloc(&g->nrm, (size_t)(P * N * N) * sizeof(uint32_t)) != hipSuccess)
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: normal allocation");
-    if (hipMalloc(&g->solid, (size_t)P) != hipSuccess)
+    if (hipMalloc(&g->solid, (size_t)P) != hipSuccess || hipMalloc(&g->octmin, (size_t)P * 8 * sizeof(float)) != hipSuccess)
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: probe flag allocation");
     if (hipMalloc(&g->counter, 64) != hipSuccess) return cleanup(PT_ERR_OUT_OF_MEMORY, "counter allocation");
     if (hipEventCreateWithFlags(&g->staging_free, hipEventDisableTiming) != hipSuccess)
@@ -247,7 +283,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         int64_t tl = P * (int64_t)(N >> l) * (N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, N, l, g->stride, tl);
     }
-    hipLaunchKernelGGL(k_probe_solid, dim3((unsigned)P), dim3(256), 0, s, g->pyr, g->stride, N * N, g->solid);
+    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)P), dim3(256), 0, s, g->pyr, g->stride, N, g->solid, g->octmin);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(PT_ERR_HIP, std::string("probe_grid_create launch: ") + hipGetErrorString(e));
     *out = g;
@@ -268,6 +304,7 @@ extern "C" void probe_grid_destroy(pt_grid *g) {
     if (g->pyr) (void)hipFree(g->pyr);
     if (g->nrm) (void)hipFree(g->nrm);
     if (g->solid) (void)hipFree(g->solid);
+    if (g->octmin) (void)hipFree(g->octmin);
     if (g->counter) (void)hipFree(g->counter);
     if (g->views_dev) (void)hipFree(g->views_dev);
     if (g->views_host) (void)hipHostFree(g->views_host);
@@ -379,67 +416,115 @@ __device__ bool eye_start_unknown(const GridDev &g, int p, const float Xp[3], fl
     return (t1 < 0.0f) || (rs2 > t1 * t1);
 }
 
+// A probe none of whose texels a piece in this cell can reach holds a stored distance below
+// the farthest point of the cell from the probe: then no texel fires for any segment of the
+// cell, and the probe answers MISS.  The region holds every segment the walk gives the
+// cell: the cell between its planes, and on an axis where the walk clamps (first or last
+// cell) everything out to the scene box and the eye.  A piece takes the octant of its
+// midpoint, one the region reaches on each axis (a piece within rounding of one of the
+// probe's planes may take the octant across it; octmin covers the texels it reaches
+// then); the 10^-3 slack on the distance covers the FP32 rounding of the radial distances
+// the march compares.
+__device__ __forceinline__ bool probe_clear(const GridDev &g, const float *om, const float O[3], const float lo[3],
+                                            const float hi[3]) {
+    float r2 = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const float e = fmaxf(fabsf(lo[a] - O[a]), fabsf(hi[a] - O[a]));
+        r2 += e * e;
+    }
+    float m = INFINITY;
+    for (int o = 0; o < 8; ++o) {
+        bool in = true;
+        for (int a = 0; a < 3; ++a) in = in && (((o >> a) & 1) ? hi[a] > O[a] : lo[a] < O[a]);
+        if (in) m = fminf(m, om[o]);
+    }
+    return m > 0.0f && m * m > r2 * 1.002001f;
+}
+
 // Cage word of every cell for every view (the eye is the same for all rays of a view): the
-// cage order, limited to its first max_probes codes.  With `solid` flags (skip enabled),
-// the probes known to answer UNKNOWN for every ray of the view that reaches them are left
-// out of the word and its UNKNOWN bit set instead: the walk's first HIT in cage order is the
-// same without them, and for a ray that hits nothing the bit marks the UNKNOWN they would
-// have given (every rank of the cell is reached then).  Those probes are the ones inside
-// solids (a stored distance <= 0 fires on any piece's first texel, behind the surface) and,
-// when `eye_cell` is set (the level whose cells are the walk's own), the probes of the
-// eye's cell whose start texel fires behind the surface (eye_start_unknown).  A probe the
-// eye sits on (within the eye radius, tested exactly as the trace tests it) stays: its eye
-// lookup may be a HIT at t = 0.  One case differs from tracing a solid probe: a segment
-// wholly within 2^-12 of the position scale of its centre, which the trace trims to nothing
-// (MISS) and the word counts UNKNOWN, the exact method's answer.
-__global__ void k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single, int n_views, int cells,
-                             const uint8_t *__restrict__ solid, int eye_cell, uint32_t *__restrict__ tab) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n_views * cells) return;
-    int v = (int)(i / cells), c = (int)(i % cells);
-    const float *X = views ? views[v].pos : single.pos;
-    int nx = g.cmax[0] + 1, ny = g.cmax[1] + 1;
-    int cell[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
-    const uint32_t order = g.few ? cage_order<true>(g, cell, X) : cage_order<false>(g, cell, X);
-    if (!solid) {
-        tab[i] = cage_word(order, g.max_probes);
-        return;
-    }
-    // the eye's cell, as the walk finds it, and the farthest any segment end can be from the
-    // eye (the scene box exit, which the walk stretches by 1e-4)
-    bool at_eye = eye_cell != 0 && g.start_test != 0;
-    float tbmax = 0.0f;
-    if (at_eye) {
-        for (int a = 0; a < 3; ++a) {
-            const float q = (X[a] - g.org[a]) * g.ispc[a];
-            at_eye = at_eye && cell[a] == min(max((int)floor(q), 0), g.cmax[a]);
+// cage order, limited to its first max_probes codes.  With the per-probe flags (`solid`,
+// `octmin`; skip enabled), probes whose answer is known for every ray of the view that
+// reaches them are left out of the word:
+// * UNKNOWN: probes inside solids (a stored distance <= 0 fires on any piece's first texel,
+//   behind the surface) and, when `own` is set (the level whose cells the walk steps
+//   through), the probes of the eye's cell whose start texel fires behind the surface
+//   (eye_start_unknown).  The word's UNKNOWN bit stands for them: the walk's first HIT in
+//   cage order is the same without them, and for a ray that hits nothing the bit marks the
+//   UNKNOWN they would have given (every rank of the cell is reached then).
+// * MISS, when `own` is set: probes clear of the whole cell (probe_clear).  A MISS changes
+//   nothing of the walk.
+// A probe the eye sits on (within the eye radius, tested exactly as the trace tests it)
+// stays: its eye lookup may be a HIT at t = 0.  One case differs from tracing a solid probe:
+// a segment wholly within 2^-12 of the position scale of its centre, which the trace trims
+// to nothing (MISS) and the word counts UNKNOWN, the exact method's answer.
+//
+// Eight lanes per (view, cell), one per cage rank, so that the per-probe loads of a cell are
+// in flight together; the first lane of each eight packs the word from two ballots.
+__global__ void __launch_bounds__(256) k_cage_order(GridDev g, const ViewDev *__restrict__ views, ViewDev single,
+                                                    int n_views, int cells, const uint8_t *__restrict__ solid,
+                                                    const float *__restrict__ octmin, int own,
+                                                    uint32_t *__restrict__ tab) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t >> 3;
+    const int rk = (int)(t & 7);
+    const bool valid = i < (int64_t)n_views * cells;
+    uint32_t order = 0;
+    bool keep = false, unknown = false;
+    if (valid) {
+        const int v = (int)(i / cells), c = (int)(i % cells);
+        const float *X = views ? views[v].pos : single.pos;
+        const int nx = g.cmax[0] + 1, ny = g.cmax[1] + 1;
+        const int cell[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+        order = g.few ? cage_order<true>(g, cell, X) : cage_order<false>(g, cell, X);
+        keep = rk < g.max_probes;
+        if (solid && keep) {
+            // the eye's cell, as the walk finds it, and the farthest any segment end can be
+            // from the eye (the scene box exit, which the walk stretches by 1e-4)
+            bool at_eye = own != 0 && g.start_test != 0;
+            float tbmax = 0.0f;
+            if (at_eye) {
+                float far2 = 0.0f;
+                for (int a = 0; a < 3; ++a) {
+                    const float q = (X[a] - g.org[a]) * g.ispc[a];
+                    at_eye = at_eye && cell[a] == min(max((int)floor(q), 0), g.cmax[a]);
+                    const float e = fmaxf(fabsf(g.smin[a] - X[a]), fabsf(g.smax[a] - X[a]));
+                    far2 += e * e;
+                }
+                tbmax = sqrtf(far2) * 1.001f + 1e-3f;
+            }
+            int pc[3];
+            cage_probe(g, g.few != 0, cell, (int)((order >> (3 * rk)) & 7u), pc);
+            const int p = pc[0] + g.n[0] * (pc[1] + g.n[1] * pc[2]);
+            float O[3], Xp[3], lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                O[a] = grid_coord<float>(g, a, pc[a]);
+                Xp[a] = X[a] - O[a];
+                // the region of the cell's segments (probe_clear)
+                const float p0 = grid_coord<float>(g, a, cell[a]), p1 = grid_coord<float>(g, a, cell[a] + 1);
+                const float ext = 1e-3f * (g.smax[a] - g.smin[a]);
+                lo[a] = cell[a] == 0 ? fminf(fminf(g.smin[a], X[a]), p0) - ext : p0;
+                hi[a] = cell[a] == g.cmax[a] ? fmaxf(fmaxf(g.smax[a], X[a]), p1) + ext : p1;
+            }
+            const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
+            if (!(d2 <= g.eye_eps2)) {
+                unknown = solid[p] || (at_eye && eye_start_unknown(g, p, Xp, tbmax));
+                keep = !unknown && !(own && probe_clear(g, octmin + (int64_t)p * 8, O, lo, hi));
+            }
         }
-        float far2 = 0.0f;
-        for (int a = 0; a < 3; ++a) {
-            const float e = fmaxf(fabsf(g.smin[a] - X[a]), fabsf(g.smax[a] - X[a]));
-            far2 += e * e;
-        }
-        tbmax = sqrtf(far2) * 1.001f + 1e-3f;
     }
-    uint32_t kept = 0, flag = 0;
-    int n = 0;
-    for (int rk = 0; rk < g.max_probes; ++rk) {
-        const int code = (int)((order >> (3 * rk)) & 7u);
-        int pc[3];
-        cage_probe(g, g.few != 0, cell, code, pc);
-        const int p = pc[0] + g.n[0] * (pc[1] + g.n[1] * pc[2]);
-        float Xp[3];
-        for (int a = 0; a < 3; ++a) Xp[a] = X[a] - grid_coord<float>(g, a, pc[a]);
-        const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
-        const bool eye_on = d2 <= g.eye_eps2;
-        if (!eye_on && (solid[p] || (at_eye && eye_start_unknown(g, p, Xp, tbmax)))) {
-            flag = kCageUnknown;
-        } else {
-            kept |= (uint32_t)code << (3 * n);
-            ++n;
-        }
+    const uint64_t kb = __ballot(keep), ub = __ballot(unknown);
+    if (valid && rk == 0) {
+        const int base = (int)(threadIdx.x & 63);
+        const uint32_t k8 = (uint32_t)(kb >> base) & 0xffu;
+        uint32_t kept = 0;
+        int n = 0;
+        for (int r = 0; r < 8; ++r)
+            if ((k8 >> r) & 1u) {
+                kept |= ((order >> (3 * r)) & 7u) << (3 * n);
+                ++n;
+            }
+        tab[i] = cage_word(kept, n) | (((ub >> base) & 0xffu) ? kCageUnknown : 0u);
     }
-    tab[i] = cage_word(kept, n) | flag;
 }
 
 // Kernel template parameters: W = 64-bit probe addressing, T = layout (kGrid, kTwoLevel:
@@ -1160,8 +1245,10 @@ struct TraceCtx {
     Level2 L2;     // coarse level (two == true)
     bool wide, two;
     int ccells;    // coarse cells
-    // per-probe solid flags of both levels, or null: the cage tables then list every probe
+    // per-probe flags and octant minima of both levels, or null: the cage tables then list
+    // every probe
     const uint8_t *solid, *csolid;
+    const float *octmin, *coctmin;
 };
 
 static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
@@ -1171,6 +1258,7 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
     c.wide = g->wide || (opts && (opts->flags & PT_FLAG_WIDE));
     const bool skip = !(opts && (opts->flags & PT_FLAG_TRACE_ALL_PROBES));
     c.solid = skip ? g->solid : nullptr;
+    c.octmin = skip ? g->octmin : nullptr;
     if (c.two) {
         make_griddev(g->coarse, opts, c.L2.c);
         for (int a = 0; a < 3; ++a) {
@@ -1180,6 +1268,7 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
         c.L2.Pf = g->P;
         c.wide = c.wide || g->coarse->wide;
         c.csolid = skip ? g->coarse->solid : nullptr;
+        c.coctmin = skip ? g->coarse->octmin : nullptr;
         c.ccells = g->coarse->cells;
     }
 }
@@ -1203,12 +1292,12 @@ static void make_ctx(const pt_grid *g, const pt_trace_opts *opts, TraceCtx &c) {
 static void launch_cage_tables(const pt_grid *g, const TraceCtx &c, const ViewDev *views_dev, const ViewDev &one,
                                int n_views, uint32_t *cage, uint32_t *ccage, hipStream_t s) {
     int64_t nc = (int64_t)n_views * g->cells;
-    hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc, 256)), dim3(256), 0, s, c.d, views_dev, one, n_views,
-                       g->cells, c.solid, 1, cage);
+    hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(nc * 8, 256)), dim3(256), 0, s, c.d, views_dev, one, n_views,
+                       g->cells, c.solid, c.octmin, 1, cage);
     if (c.two) {
         int64_t ncc = (int64_t)n_views * c.ccells;
-        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(ncc, 256)), dim3(256), 0, s, c.L2.c, views_dev, one,
-                           n_views, c.ccells, c.csolid, 0, ccage);
+        hipLaunchKernelGGL(k_cage_order, dim3(blocks_for(ncc * 8, 256)), dim3(256), 0, s, c.L2.c, views_dev, one,
+                           n_views, c.ccells, c.csolid, c.coctmin, 0, ccage);
     }
 }
 
@@ -1683,6 +1772,7 @@ static pt_status launch_soft(const pt_grid *g, const pt_view *views_host, int32_
     // a probe inside a solid can still give a candidate (its first firing texel may face
     // the ray): the soft walk traces every probe
     c.solid = c.csolid = nullptr;
+    c.octmin = c.coctmin = nullptr;
     launch_cage_tables(g, c, mg->views_dev, ViewDev{}, n_views, mg->cage, mg->ccage, s);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, mg->counter);
 #define PT_LAUNCH(W, T)                                                                                       \
@@ -1839,7 +1929,8 @@ extern "C" pt_status probe_grid_set_distance(pt_grid *g, const float *distance_d
         int64_t tl = (int64_t)g->P * (int64_t)(g->N >> l) * (g->N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, g->N, l, g->stride, tl);
     }
-    hipLaunchKernelGGL(k_probe_solid, dim3((unsigned)g->P), dim3(256), 0, s, g->pyr, g->stride, g->N * g->N, g->solid);
+    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)g->P), dim3(256), 0, s, g->pyr, g->stride, g->N, g->solid,
+                       g->octmin);
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }

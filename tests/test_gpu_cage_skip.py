@@ -1,11 +1,14 @@
-"""Probes the per-view cage tables leave out of the hard walk, because they answer UNKNOWN
+"""Probes the per-view cage tables leave out of the hard walk, because their answer is known
 for every ray of the view that reaches them (PT_FLAG_TRACE_ALL_PROBES traces them):
-probes inside solids (every stored distance <= 0) and, in the eye's cell, probes whose
-first texel fires behind the stored surface for the eye itself.  Checked here: the same
-outputs bit for bit either way on the city block, where most probes of both levels sit
-inside buildings, in every launch form and in the adjoints; on the room, the 64-view walk
-and the paper's 2048^2 maps, where the eye's cell gives such probes; a probe the eye sits
-on is still traced (its eye lookup is a HIT at t = 0); the flags follow
+UNKNOWN for probes inside solids (every stored distance <= 0) and, in the eye's cell, for
+probes whose first texel fires behind the stored surface for the eye itself; MISS for
+probes whose nearest stored surface in every octant a piece of the cell can take lies
+beyond the cell's farthest point.  Checked here: the same outputs bit for bit either way
+on the city block, where most probes of both levels sit inside buildings, in every launch
+form and in the adjoints; on the room, the 64-view walk and the paper's 2048^2 maps, where
+the eye's cell gives such probes; on the sparse differentiable grid, where many probes are
+clear of their cells, also after probe_grid_set_distance moves the surfaces; a probe the
+eye sits on is still traced (its eye lookup is a HIT at t = 0); the flags follow
 probe_grid_set_distance (zeroed, negative and NaN maps); and a layout of fewer than 8
 probes.  Each default result is also held to the oracle."""
 import dataclasses
@@ -214,3 +217,42 @@ def test_eye_cell_skip_gives_identical_results(name, kw, nviews):
     assert (err <= 1e-5 * grads[2] + 1e-7).all(), (err / (grads[2] + 1e-7)).max()
     assert np.array_equal(grads[0] != 0, grads[1] != 0)
     assert np.count_nonzero(grads[1]) > 1000
+
+
+def test_clear_probes_skip_gives_identical_results():
+    # the sparse 16x16x8 grid (reduced maps): a large share of its probes are clear of their
+    # cells; then the same distances pulled in to half, where far fewer are
+    pt = _pt()
+    scene, probes, views = workload("diff", N=64, levels=4, n_views=2, size=(160, 128))
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad16 = probes.radiance.view(np.float16)
+    rad = torch.from_numpy(rad16.copy()).cuda()
+    rays = sum(v.width * v.height for v in views)
+    g = torch.from_numpy(np.random.default_rng(6).normal(size=(rays, 3)).astype(np.float32)).cuda()
+    gt = torch.from_numpy(np.random.default_rng(7).normal(size=rays).astype(np.float32)).cuda()
+    P, N = probes.n_probes, probes.N
+    for scale in (1.0, 0.5):
+        if scale != 1.0:
+            grid.set_distance(torch.from_numpy((probes.distance * scale).astype(np.float32)).cuda())
+        ref = _np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=pt.PT_FLAG_TRACE_ALL_PROBES)))
+        for flags in (0, pt.PT_FLAG_PERSISTENT, pt.PT_FLAG_GRAPH):
+            _same(_np(pt.probe_trace(grid, rad, views, pt.trace_opts(flags=flags))), ref, (scale, flags))
+        if scale == 1.0:
+            og = oracle.Grid.from_probes(probes)
+            o = np.concatenate([oracle.view_rays(*v.as_tuple())[0] for v in views])
+            d = np.concatenate([oracle.view_rays(*v.as_tuple())[1] for v in views])
+            assert_parity(compare(ref, oracle.trace(og, o, d)), "sparse grid, clear probes left out")
+        res = []
+        for flags, gg in ((0, g), (pt.PT_FLAG_TRACE_ALL_PROBES, g), (pt.PT_FLAG_TRACE_ALL_PROBES, g.abs())):
+            gr = torch.zeros((P, N, N, 3), device="cuda")
+            pt.probe_trace_backward(grid, views, gg, gr, pt.trace_opts(flags=flags | pt.PT_FLAG_PERSISTENT))
+            gd = torch.zeros((P, N, N), device="cuda")
+            pt.probe_trace_backward_distance(grid, rad, views, g, gt, gd, pt.trace_opts(flags=flags))
+            res.append((gr.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64)))
+        # radiance: bounded by the adjoint of |g| (every term positive); distance: its terms
+        # carry signed d rgb / d t, so relative to the texel's value and the largest one
+        tols = (1e-5 * res[2][0] + 1e-7, 1e-4 * np.abs(res[1][1]) + 1e-6 * np.abs(res[1][1]).max())
+        for k in range(2):
+            err = np.abs(res[0][k] - res[1][k])
+            assert (err <= tols[k]).all(), (scale, k, (err / tols[k]).max())
+            assert np.array_equal(res[0][k] != 0, res[1][k] != 0), (scale, k)
