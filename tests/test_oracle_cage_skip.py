@@ -1,0 +1,80 @@
+"""The premise of the cage tables' clear-probe rule, checked against the oracle's own walk
+(no GPU): a probe whose smallest stored distance, over the texels a piece in each octant
+the cell region admits can reach, exceeds the region's farthest point from the probe has
+no level-0 texel that fires along any segment the grid iterator gives that cell.  The rule
+is restated here from its definition (octant triangles of the octahedral map with a band
+across the fold, the neighbouring quadrants' edge texels, the cell region clamped out to
+the scene box and the eye) and each certified (ray, cell, probe) is checked on the flat
+level-0 texel sequence in double precision: every texel's stored distance is at least the
+radial distance at both ends of its span."""
+import numpy as np
+
+import oracle
+from conftest import workload
+
+
+def _octant_minima(D):
+    """[P][8] minima, octant o = [x >= 0] + 2 [y >= 0] + 4 [z >= 0]."""
+    P, N, _ = D.shape
+    h = N // 2
+    i = np.arange(N)
+    sx = (i >= h).astype(int)
+    a = np.where(sx == 1, i - h, h - 1 - i)
+    out = np.full((P, 8), np.inf)
+    Dn = np.where(np.isnan(D), np.inf, D)
+    for o in range(8):
+        ox, oy, oz = o & 1, (o >> 1) & 1, o >> 2
+        A = a[None, :]          # column (x) index -> a
+        B = a[:, None]          # row (y) index -> b
+        SX = sx[None, :]
+        SY = sx[:, None]
+        own = (SX == ox) & (SY == oy)
+        edge = ((SX == ox) | (A == 0)) & ((SY == oy) | (B == 0))
+        tri = (A + B <= h + 1) if oz else (A + B >= h - 3)
+        mask = (own & tri) | (~own & edge)
+        out[:, o] = np.where(mask[None], Dn, np.inf).reshape(P, -1).min(1)
+    return out
+
+
+def test_clear_probes_never_fire_on_their_cells():
+    scene, probes, views = workload("diff", N=32, levels=3, n_views=1, size=(40, 32))
+    og = oracle.Grid.from_probes(probes)
+    N, P = probes.N, probes.n_probes
+    D = probes.distance.reshape(P, N, N).astype(np.float64)
+    om = _octant_minima(D)
+    nx, ny, nz = probes.dims
+    cmax = np.array(probes.dims) - 2
+    org, spc = np.array(probes.origin, float), np.array(probes.spacing, float)
+    smin, smax = np.array(probes.scene_min, float), np.array(probes.scene_max, float)
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    rng = np.random.default_rng(0)
+    certified = checked_texels = 0
+    for r in rng.choice(len(o), 400, replace=False):
+        X, w = o[r], d[r]
+        cells, iv = oracle.cell_walk(og, X, w)
+        for cell, (ta, tb) in zip(cells, iv):
+            lo = org + cell * spc
+            hi = lo + spc
+            for a in range(3):
+                ext = 1e-3 * (smax[a] - smin[a])
+                if cell[a] == 0:
+                    lo[a] = min(smin[a], X[a], lo[a]) - ext
+                if cell[a] == cmax[a]:
+                    hi[a] = max(smax[a], X[a], hi[a]) + ext
+            for code in range(8):
+                pc = cell + np.array([code & 1, (code >> 1) & 1, code >> 2])
+                p = pc[0] + nx * (pc[1] + ny * pc[2])
+                O = org + pc * spc
+                R2 = (np.maximum(np.abs(lo - O), np.abs(hi - O)) ** 2).sum()
+                octs = [oo for oo in range(8)
+                        if all((hi[a] > O[a]) if (oo >> a) & 1 else (lo[a] < O[a]) for a in range(3))]
+                m = min(om[p, oo] for oo in octs)
+                if not (m > 0 and m * m > R2 * 1.002001):
+                    continue
+                certified += 1
+                ij, tio, _ = oracle.texel_sequence(N, X - O, w, ta, tb)
+                rho = np.linalg.norm((X - O)[None, None, :] + tio[:, :, None] * w[None, None, :], axis=2)
+                stored = D[p, ij[:, 1], ij[:, 0]]
+                assert np.all(stored >= rho.max(1)), (r, cell, code)
+                checked_texels += len(ij)
+    assert certified > 300 and checked_texels > 3000, (certified, checked_texels)
