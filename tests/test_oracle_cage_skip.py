@@ -1,12 +1,15 @@
-"""The premise of the cage tables' clear-probe rule, checked against the oracle's own walk
-(no GPU): a probe whose smallest stored distance, over the texels a piece in each octant
-the cell region admits can reach, exceeds the region's farthest point from the probe has
-no level-0 texel that fires along any segment the grid iterator gives that cell.  The rule
-is restated here from its definition (octant triangles of the octahedral map with a band
-across the fold, the neighbouring quadrants' edge texels, the cell region clamped out to
-the scene box and the eye) and each certified (ray, cell, probe) is checked on the flat
+"""The premises of the cage tables' known-answer rules, checked against the oracle's own walk
+(no GPU).  Clear probes: a probe whose smallest stored distance, over the texels a piece in
+each octant the cell region admits can reach, exceeds the region's farthest point from the
+probe has no level-0 texel that fires along any segment the grid iterator gives that cell.
+The rule is restated here from its definition (octant triangles of the octahedral map with
+a band across the fold, the neighbouring quadrants' edge texels, the cell region clamped out
+to the scene box and the eye) and each certified (ray, cell, probe) is checked on the flat
 level-0 texel sequence in double precision: every texel's stored distance is at least the
-radial distance at both ends of its span."""
+radial distance at both ends of its span.  Eye cell: every ray's walk starts in the eye's
+cell at t = 0, and its first texel there is the texel of the eye's own direction from the
+probe, so a probe whose stored distance in that direction lies below the eye's radial
+distance (shadow-entry rule) answers UNKNOWN for every ray of the view."""
 import numpy as np
 
 import oracle
@@ -78,3 +81,39 @@ def test_clear_probes_never_fire_on_their_cells():
                 assert np.all(stored >= rho.max(1)), (r, cell, code)
                 checked_texels += len(ij)
     assert certified > 300 and checked_texels > 3000, (certified, checked_texels)
+
+
+def test_eye_cell_probes_behind_the_surface_answer_unknown_for_every_ray():
+    # the eye-cell rule: every ray's first piece in the eye's cell starts at the eye, in the
+    # eye's octant, so its first texel is the texel of X - O itself; when that texel's stored
+    # distance is below |X - O| / (1 + tau), the first fire is behind the surface (UNKNOWN)
+    scene, probes, views = workload("single", size=(64, 36))
+    og = oracle.Grid.from_probes(probes)
+    N, P = probes.N, probes.n_probes
+    D = probes.distance.reshape(P, N, N).astype(np.float64)
+    tau1 = 1.0 + 8.0 / N
+    X = np.asarray(views[0].pos, np.float64)
+    org, spc = np.array(probes.origin, float), np.array(probes.spacing, float)
+    nx, ny, _ = probes.dims
+    cell = np.clip(np.floor((X - org) / spc).astype(int), 0, np.array(probes.dims) - 2)
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    rng = np.random.default_rng(1)
+    rays = rng.choice(len(o), 300, replace=False)
+    flagged = 0
+    for code in range(8):
+        pc = cell + np.array([code & 1, (code >> 1) & 1, code >> 2])
+        p = pc[0] + nx * (pc[1] + ny * pc[2])
+        xp = X - (org + pc * spc)
+        u, v = oracle.oct_encode(xp)
+        i, j = (min(int(np.floor((c + 1.0) * 0.5 * N)), N - 1) for c in (u, v))
+        r = D[p, j, i]
+        rho0 = np.linalg.norm(xp)
+        if not (r < rho0 and rho0 > r * tau1):
+            continue
+        flagged += 1
+        for k in rays:
+            cells, iv = oracle.cell_walk(og, o[k], d[k])
+            assert np.array_equal(cells[0], cell) and iv[0, 0] == 0.0
+            ij, tio, _ = oracle.texel_sequence(N, xp, d[k], 0.0, iv[0, 1])
+            assert tuple(ij[0]) == (i, j) and tio[0, 0] == 0.0, (p, k, ij[0], (i, j))
+    assert flagged >= 2, flagged
