@@ -416,17 +416,15 @@ __device__ bool eye_start_unknown(const GridDev &g, int p, const float Xp[3], fl
     return (t1 < 0.0f) || (rs2 > t1 * t1);
 }
 
-// A probe none of whose texels a piece in this cell can reach holds a stored distance below
-// the farthest point of the cell from the probe: then no texel fires for any segment of the
-// cell, and the probe answers MISS.  The region holds every segment the walk gives the
-// cell: the cell between its planes, and on an axis where the walk clamps (first or last
-// cell) everything out to the scene box and the eye.  A piece takes the octant of its
-// midpoint, one the region reaches on each axis (a piece within rounding of one of the
-// probe's planes may take the octant across it; octmin covers the texels it reaches
-// then); the 10^-3 slack on the distance covers the FP32 rounding of the radial distances
-// the march compares.
-__device__ __forceinline__ bool probe_clear(const GridDev &g, const float *om, const float O[3], const float lo[3],
-                                            const float hi[3]) {
+// When no texel that a piece in this cell can reach holds a stored distance below the cell's
+// farthest point from the probe, no texel fires for any segment of the cell and the probe
+// answers MISS.  The region [lo, hi] holds every segment the walk gives the cell: the cell
+// between its planes, and on an axis where the walk clamps (first or last cell) everything
+// out to the scene box and the eye.  A piece takes the octant of its midpoint, one the
+// region reaches on each axis (a piece within rounding of one of the probe's planes may
+// take the octant across it; octmin covers the texels it reaches then).  The 10^-3 slack
+// on the distance covers the FP32 rounding of the radial distances the march compares.
+__device__ __forceinline__ bool probe_clear(const float *om, const float O[3], const float lo[3], const float hi[3]) {
     float r2 = 0.0f;
     for (int a = 0; a < 3; ++a) {
         const float e = fmaxf(fabsf(lo[a] - O[a]), fabsf(hi[a] - O[a]));
@@ -508,7 +506,7 @@ __global__ void __launch_bounds__(256) k_cage_order(GridDev g, const ViewDev *__
             const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
             if (!(d2 <= g.eye_eps2)) {
                 unknown = solid[p] || (at_eye && eye_start_unknown(g, p, Xp, tbmax));
-                keep = !unknown && !(own && probe_clear(g, octmin + (int64_t)p * 8, O, lo, hi));
+                keep = !unknown && !(own && probe_clear(octmin + (int64_t)p * 8, O, lo, hi));
             }
         }
     }
