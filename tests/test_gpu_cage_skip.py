@@ -7,8 +7,9 @@ beyond the cell's farthest point.  Checked here: the same outputs bit for bit ei
 on the city block, where most probes of both levels sit inside buildings, in every launch
 form and in the adjoints; on the room, the 64-view walk and the paper's 2048^2 maps, where
 the eye's cell gives such probes; on the sparse differentiable grid, where many probes are
-clear of their cells, also after probe_grid_set_distance moves the surfaces; a probe the
-eye sits on is still traced (its eye lookup is a HIT at t = 0); the flags follow
+clear of their cells, also after probe_grid_set_distance moves the surfaces, and for an
+eye outside the scene box or on probe planes; a probe the eye sits on is still traced (its
+eye lookup is a HIT at t = 0); the flags follow
 probe_grid_set_distance (zeroed, negative and NaN maps); and a layout of fewer than 8
 probes.  Each default result is also held to the oracle."""
 import dataclasses
@@ -256,3 +257,50 @@ def test_clear_probes_skip_gives_identical_results():
             err = np.abs(res[0][k] - res[1][k])
             assert (err <= tols[k]).all(), (scale, k, (err / tols[k]).max())
             assert np.array_equal(res[0][k] != 0, res[1][k] != 0), (scale, k)
+
+
+def _look_at(pos, target, w, h, tan_half=0.6):
+    import synth
+    pos, target = np.asarray(pos, np.float64), np.asarray(target, np.float64)
+    fwd = target - pos
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, [0.0, 0.0, 1.0])
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    return synth.View(pos.astype(np.float32).astype(np.float64), right, up, fwd, tan_half, w, h)
+
+
+@pytest.mark.parametrize("where", ["outside_the_box", "on_probe_planes"])
+def test_known_answer_skip_with_unusual_eyes(where):
+    # eyes the region and octant rules must allow for: outside the scene box (the walk's
+    # first cells are clamped and their segments start far from the grid) and exactly on
+    # probe planes along x and z (pieces in those planes take the octant across)
+    pt = _pt()
+    scene, probes, views = workload("diff", N=64, levels=4, n_views=1, size=(64, 64))
+    grid = pt.ProbeGrid.from_probes(probes)
+    rad = torch.from_numpy(probes.radiance.view(np.float16).copy()).cuda()
+    room = np.asarray(scene.room_max, np.float64)
+    if where == "outside_the_box":
+        v = _look_at(room + np.array([3.0, 2.0, 1.5]), 0.5 * room, 160, 120)
+    else:
+        org, spc = np.asarray(probes.origin, np.float64), np.asarray(probes.spacing, np.float64)
+        pos = np.array([org[0] + 5 * spc[0], 0.37 * room[1], org[2] + 3 * spc[2]])
+        v = _look_at(pos, pos + np.array([0.0, 5.0, 0.0]), 160, 120)
+    a = _np(pt.probe_trace(grid, rad, [v]))
+    b = _np(pt.probe_trace(grid, rad, [v], pt.trace_opts(flags=pt.PT_FLAG_TRACE_ALL_PROBES)))
+    _same(a, b, where)
+    orc = oracle.trace_view(oracle.Grid.from_probes(probes), v.as_tuple())
+    s = compare(a, orc)
+    if where == "outside_the_box":
+        assert_parity(s, f"unusual eye: {where}")
+    else:
+        # an eye on probe planes makes every ray an exact tie of the kind the degenerate-ray
+        # tests cover, held to their bar: every disagreement in the margin, at most 1%, and
+        # every reported HIT valid
+        from degenerate import hit_is_valid
+        info = {k: val for k, val in s.items() if k != "disagree_idx"}
+        print(f"[parity] unusual eye: {where} {info}", flush=True)
+        assert s["disagree_outside_margin"] == 0 and s["disagree"] <= 0.01 * s["n"], info
+        o, d = oracle.view_rays(*v.as_tuple())
+        assert hit_is_valid(probes, o, d, a["status"], a["hit"], a["t"], 8.0 / probes.N).all()
+        assert (a["status"] == oracle.HIT).mean() > 0.5
