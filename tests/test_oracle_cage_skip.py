@@ -9,7 +9,9 @@ level-0 texel sequence in double precision: every texel's stored distance is at 
 radial distance at both ends of its span.  Eye cell: every ray's walk starts in the eye's
 cell at t = 0, and its first texel there is the texel of the eye's own direction from the
 probe, so a probe whose stored distance in that direction lies below the eye's radial
-distance (shadow-entry rule) answers UNKNOWN for every ray of the view."""
+distance (shadow-entry rule) answers UNKNOWN for every ray of the view.  Solid probes: with
+every stored distance <= 0 the oracle's walk answers UNKNOWN for every ray, and HIT at
+t = 0 for an eye on a probe."""
 import numpy as np
 
 import oracle
@@ -117,3 +119,22 @@ def test_eye_cell_probes_behind_the_surface_answer_unknown_for_every_ray():
             ij, tio, _ = oracle.texel_sequence(N, xp, d[k], 0.0, iv[0, 1])
             assert tuple(ij[0]) == (i, j) and tio[0, 0] == 0.0, (p, k, ij[0], (i, j))
     assert flagged >= 2, flagged
+
+
+def test_solid_probes_answer_unknown_for_every_ray():
+    # the solid-probe rule: with every stored distance <= 0, each probe's first texel fires
+    # behind the surface, so every ray is UNKNOWN unless the eye sits on a probe (its eye
+    # lookup returns the stored 0, a HIT at t = 0)
+    scene, probes, views = workload("tiny")
+    P, N = probes.n_probes, probes.N
+    d0 = np.zeros_like(probes.distance)
+    d0[1] = -0.25
+    og = oracle.Grid(probes.dims, probes.origin, probes.spacing, N, probes.levels, probes.scene_min,
+                     probes.scene_max, d0, probes.normal, probes.radiance.view(np.float16).astype(np.float32))
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    res = oracle.trace(og, o, d)
+    assert np.all(res["status"] == oracle.UNKNOWN)
+    # an eye on probe 0
+    O = og.probe_position(0)
+    res = oracle.trace(og, np.repeat(O[None], len(d), 0), d)
+    assert np.all(res["status"] == oracle.HIT) and np.all(res["t"] == 0.0) and np.all(res["probe"] == 0)
