@@ -138,3 +138,107 @@ def test_solid_probes_answer_unknown_for_every_ray():
     O = og.probe_position(0)
     res = oracle.trace(og, np.repeat(O[None], len(d), 0), d)
     assert np.all(res["status"] == oracle.HIT) and np.all(res["t"] == 0.0) and np.all(res["probe"] == 0)
+
+
+def _texel_reach(N, spc, o):
+    """[N][N] bound on the radial distance at which a direction of each texel of octant o
+    leaves a cell of the spacing with the probe at its corner: min over the axes of
+    spacing / |w_i|, |w_i| at its smallest over the texel's corners (the ratio |p_i| / |p| of
+    the decoded direction is quasi-concave on a texel inside one octant triangle).  Texels
+    across the fold take the cell's diagonal."""
+    h = N // 2
+    R = float(np.linalg.norm(spc))
+    idx = np.arange(N)
+    a = np.where(idx >= h, idx - h, h - 1 - idx)
+    A, B = a[None, :] + 0 * a[:, None], a[:, None] + 0 * a[None, :]
+    oz = o >> 2
+    inside = (A + B + 2 <= h) if oz else (A + B >= h)
+    m = np.full((N, N, 3), np.inf)
+    for da in (0, 1):
+        for db in (0, 1):
+            au, bv = (A + da) * (2.0 / N), (B + db) * (2.0 / N)
+            p = np.stack([au, bv, 1.0 - au - bv], -1) if oz else np.stack([1.0 - bv, 1.0 - au, au + bv - 1.0], -1)
+            m = np.minimum(m, np.abs(p) / np.linalg.norm(p, axis=-1, keepdims=True))
+    with np.errstate(divide="ignore"):
+        r_in = np.min(np.asarray(spc, float)[None, None, :] / m, axis=-1)
+    return np.where(inside, np.minimum(r_in, R), R)
+
+
+def _directional_minima(D, spc):
+    """[P][8] minima of D / reach over the texels a piece in each octant reaches (the octant
+    triangle, the fold band and the neighbouring quadrants' edge texels, as octmin)."""
+    P, N, _ = D.shape
+    h = N // 2
+    idx = np.arange(N)
+    sx = idx >= h
+    a = np.where(sx, idx - h, h - 1 - idx)
+    A, B = a[None, :], a[:, None]
+    SX, SY = sx[None, :], sx[:, None]
+    Dn = np.where(np.isnan(D), np.inf, D)
+    out = np.full((P, 8), np.inf)
+    for o in range(8):
+        ox, oy, oz = o & 1, (o >> 1) & 1, o >> 2
+        reach = _texel_reach(N, spc, o)
+        own = (SX == ox) & (SY == oy)
+        edge = ((SX == ox) | (A == 0)) & ((SY == oy) | (B == 0))
+        tri = (A + B <= h + 1) if oz else (A + B >= h - 3)
+        mask = (own & tri) | (~own & edge)
+        out[:, o] = np.where(mask[None], Dn / reach[None], np.inf).reshape(P, -1).min(1)
+    return out
+
+
+def test_texel_reach_bounds_every_direction_of_the_texel():
+    # sampled directions of every texel (quadrant x >= 0, y >= 0; both z halves) leave the
+    # cell [0, s] no farther than the texel's reach
+    N, spc = 16, np.array([1.0, 1.3, 0.8])
+    rng = np.random.default_rng(4)
+    for o in (3, 7):
+        reach = _texel_reach(N, spc, o)
+        for j in range(N // 2, N):
+            for i in range(N // 2, N):
+                uv = (np.array([i, j])[None, :] + rng.uniform(0, 1, size=(64, 2))) * (2.0 / N) - 1.0
+                for u, v in uv:
+                    z = 1 - abs(u) - abs(v)
+                    if (z >= 0) != bool(o >> 2):
+                        continue
+                    w = np.abs(oracle.oct_decode(np.array([u, v])))
+                    w /= np.linalg.norm(w)
+                    exit_t = min(spc[k] / w[k] for k in range(3) if w[k] > 0)
+                    assert exit_t <= reach[j, i] * (1 + 1e-12), (o, i, j, u, v, exit_t, reach[j, i])
+
+
+def test_directional_clear_probes_never_fire_on_interior_cells():
+    # the directional form of the clear rule on cells away from the grid's boundary (their
+    # region is the cell itself, one octant of each corner probe)
+    scene, probes, views = workload("diff", N=32, levels=3, n_views=1, size=(40, 32))
+    og = oracle.Grid.from_probes(probes)
+    N, P = probes.N, probes.n_probes
+    D = probes.distance.reshape(P, N, N).astype(np.float64)
+    spc = np.array(probes.spacing, float)
+    dm = _directional_minima(D, spc)
+    om = _octant_minima(D)
+    nx, ny, nz = probes.dims
+    cmax = np.array(probes.dims) - 2
+    org = np.array(probes.origin, float)
+    o, d = oracle.view_rays(*views[0].as_tuple())
+    rng = np.random.default_rng(2)
+    certified = extra = 0
+    for r in rng.choice(len(o), 400, replace=False):
+        X, w = o[r], d[r]
+        cells, iv = oracle.cell_walk(og, X, w)
+        for cell, (ta, tb) in zip(cells, iv):
+            if not np.all((cell > 0) & (cell < cmax)):
+                continue
+            for code in range(8):
+                pc = cell + np.array([code & 1, (code >> 1) & 1, code >> 2])
+                p = pc[0] + nx * (pc[1] + ny * pc[2])
+                oct_ = (1 - (code & 1)) + 2 * (1 - ((code >> 1) & 1)) + 4 * (1 - (code >> 2))
+                if not dm[p, oct_] > 1.001:
+                    continue
+                certified += 1
+                extra += not (om[p, oct_] > 1.001 * np.linalg.norm(spc))
+                O = org + pc * spc
+                ij, tio, _ = oracle.texel_sequence(N, X - O, w, ta, tb)
+                rho = np.linalg.norm((X - O)[None, None, :] + tio[:, :, None] * w[None, None, :], axis=2)
+                assert np.all(D[p, ij[:, 1], ij[:, 0]] >= rho.max(1)), (r, cell, code)
+    assert certified > 300 and extra > 20, (certified, extra)
