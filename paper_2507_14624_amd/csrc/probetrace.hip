@@ -92,7 +92,8 @@ struct pt_grid {
     float *pyr = nullptr;
     uint32_t *nrm = nullptr;
     uint8_t *solid = nullptr;  // [P] 1 for a probe whose stored distances are all <= 0
-    float *octmin = nullptr;   // [P][8] smallest stored distance per octant (k_probe_flags)
+    float *octmin = nullptr;   // [P][16] per octant: smallest stored distance, then the
+                               // smallest ratio to the texel's reach (k_probe_flags)
     // multi-view launches: view table and tile counter
     ViewDev *views_dev = nullptr;
     ViewDev *views_host = nullptr;  // pinned staging
@@ -156,14 +157,38 @@ __global__ void k_mip(float *__restrict__ pyr, int N, int l, int64_t stride, int
 //   one of the probe's axis planes may take the octant across it, and then reaches only
 //   those).  In texel units from the quadrant's centre corner a texel spans a..a+1 and
 //   b..b+1, and the fold is a + b = N/2.
-__global__ void __launch_bounds__(256) k_probe_flags(const float *__restrict__ pyr, int64_t stride, int N,
-                                                     uint8_t *__restrict__ solid, float *__restrict__ octmin) {
-    __shared__ float red[8][256];
+// * octmin[8 + o]: over the same texels, the smallest ratio of the stored distance to the
+//   texel's reach in a cell of the grid spacing with the probe at its corner (texel_reach).
+__device__ __forceinline__ float texel_reach(int a, int b, bool zpos, int N, const float spc[3], float diag) {
+    const int h = N >> 1;
+    if (zpos ? a + b + 2 > h : a + b < h) return diag;  // across the fold: the cell's diagonal
+    // along a direction w the cell [0, s] is left at min over the axes of s_i / |w_i|; over a
+    // texel inside one octant triangle |w_i| = |p_i| / |p| is smallest at a corner
+    float m[3] = {INFINITY, INFINITY, INFINITY};
+    const float step = 2.0f / (float)N;
+    for (int c = 0; c < 4; ++c) {
+        const float au = (float)(a + (c & 1)) * step, bv = (float)(b + (c >> 1)) * step;
+        const float p[3] = {zpos ? au : 1.0f - bv, zpos ? bv : 1.0f - au, zpos ? 1.0f - au - bv : au + bv - 1.0f};
+        const float inv = 1.0f / sqrtf(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        for (int k = 0; k < 3; ++k) m[k] = fminf(m[k], fabsf(p[k]) * inv);
+    }
+    float r = diag;
+    for (int k = 0; k < 3; ++k)
+        if (m[k] > 0.0f) r = fminf(r, spc[k] / m[k]);
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_probe_flags(const float *__restrict__ pyr, int64_t stride, int N, float sx_,
+                                                     float sy_, float sz_, uint8_t *__restrict__ solid,
+                                                     float *__restrict__ octmin) {
+    __shared__ float red[16][256];
     const float *d = pyr + (int64_t)blockIdx.x * stride;
     const int h = N >> 1, NN = N * N;
+    const float spc[3] = {sx_, sy_, sz_};
+    const float diag = sqrtf(sx_ * sx_ + sy_ * sy_ + sz_ * sz_);
     int ok = 1;
-    float m[8];
-    for (int o = 0; o < 8; ++o) m[o] = INFINITY;
+    float m[16];
+    for (int o = 0; o < 16; ++o) m[o] = INFINITY;
     for (int k = threadIdx.x; k < NN; k += 256) {
         const float x = d[k];
         ok &= x <= 0.0f ? 1 : 0;
@@ -176,18 +201,21 @@ __global__ void __launch_bounds__(256) k_probe_flags(const float *__restrict__ p
             const bool own = ox == sx && oy == sy;
             const bool edge = (ox == sx || a == 0) && (oy == sy || b == 0);
             const bool tri = oz ? a + b <= h + 1 : a + b >= h - 3;
-            if ((own && tri) || (!own && edge)) m[o] = fminf(m[o], x);
+            if ((own && tri) || (!own && edge)) {
+                m[o] = fminf(m[o], x);
+                m[8 + o] = fminf(m[8 + o], x / (own ? texel_reach(a, b, oz != 0, N, spc, diag) : diag));
+            }
         }
     }
     ok = __syncthreads_and(ok);
-    for (int o = 0; o < 8; ++o) red[o][threadIdx.x] = m[o];
+    for (int o = 0; o < 16; ++o) red[o][threadIdx.x] = m[o];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            for (int o = 0; o < 8; ++o) red[o][threadIdx.x] = fminf(red[o][threadIdx.x], red[o][threadIdx.x + w]);
+            for (int o = 0; o < 16; ++o) red[o][threadIdx.x] = fminf(red[o][threadIdx.x], red[o][threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x < 8) octmin[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 16) octmin[(int64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x][0];
     if (threadIdx.x == 0) solid[blockIdx.x] = (uint8_t)ok;
 }
 
@@ -271,7 +299,7 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: pyramid allocation");
     if (hipMalloc(&g->nrm, (size_t)(P * N * N) * sizeof(uint32_t)) != hipSuccess)
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: normal allocation");
-    if (hipMalloc(&g->solid, (size_t)P) != hipSuccess || hipMalloc(&g->octmin, (size_t)P * 8 * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&g->solid, (size_t)P) != hipSuccess || hipMalloc(&g->octmin, (size_t)P * 16 * sizeof(float)) != hipSuccess)
         return cleanup(PT_ERR_OUT_OF_MEMORY, "probe_grid_create: probe flag allocation");
     if (hipMalloc(&g->counter, 64) != hipSuccess) return cleanup(PT_ERR_OUT_OF_MEMORY, "counter allocation");
     if (hipEventCreateWithFlags(&g->staging_free, hipEventDisableTiming) != hipSuccess)
@@ -283,7 +311,8 @@ extern "C" pt_status probe_grid_create(const pt_grid_desc *desc, const float *di
         int64_t tl = P * (int64_t)(N >> l) * (N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, N, l, g->stride, tl);
     }
-    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)P), dim3(256), 0, s, g->pyr, g->stride, N, g->solid, g->octmin);
+    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)P), dim3(256), 0, s, g->pyr, g->stride, N, desc->spacing[0],
+                       desc->spacing[1], desc->spacing[2], g->solid, g->octmin);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(PT_ERR_HIP, std::string("probe_grid_create launch: ") + hipGetErrorString(e));
     *out = g;
@@ -449,8 +478,9 @@ __device__ __forceinline__ bool probe_clear(const float *om, const float O[3], c
 //   (eye_start_unknown).  The word's UNKNOWN bit stands for them: the walk's first HIT in
 //   cage order is the same without them, and for a ray that hits nothing the bit marks the
 //   UNKNOWN they would have given (every rank of the cell is reached then).
-// * MISS, when `own` is set: probes clear of the whole cell (probe_clear).  A MISS changes
-//   nothing of the walk.
+// * MISS, when `own` is set: probes clear of the whole cell (probe_clear; on a cell away
+//   from the grid's boundary, each texel against its own reach, octmin[8 + o]).  A MISS
+//   changes nothing of the walk.
 // A probe the eye sits on (within the eye radius, tested exactly as the trace tests it)
 // stays: its eye lookup may be a HIT at t = 0.  One case differs from tracing a solid probe:
 // a segment wholly within 2^-12 of the position scale of its centre, which the trace trims
@@ -506,7 +536,14 @@ __global__ void __launch_bounds__(256) k_cage_order(GridDev g, const ViewDev *__
             const float d2 = fmar(Xp[2], Xp[2], fmar(Xp[1], Xp[1], Xp[0] * Xp[0]));
             if (!(d2 <= g.eye_eps2)) {
                 unknown = solid[p] || (at_eye && eye_start_unknown(g, p, Xp, tbmax));
-                keep = !unknown && !(own && probe_clear(octmin + (int64_t)p * 8, O, lo, hi));
+                // a cell away from the grid's boundary is one octant of each corner probe, with
+                // the grid spacing: there the texels' own reach decides (octmin[8 + o])
+                const float *om = octmin + (int64_t)p * 16;
+                bool inner = true;
+                for (int a = 0; a < 3; ++a) inner = inner && cell[a] > 0 && cell[a] < g.cmax[a];
+                const int oc = ~(int)((order >> (3 * rk)) & 7u) & 7;
+                const bool clear = inner ? om[8 + oc] > 1.001f : probe_clear(om, O, lo, hi);
+                keep = !unknown && !(own && clear);
             }
         }
     }
@@ -1927,8 +1964,8 @@ extern "C" pt_status probe_grid_set_distance(pt_grid *g, const float *distance_d
         int64_t tl = (int64_t)g->P * (int64_t)(g->N >> l) * (g->N >> l);
         hipLaunchKernelGGL(k_mip, dim3(blocks_for(tl, 256)), dim3(256), 0, s, g->pyr, g->N, l, g->stride, tl);
     }
-    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)g->P), dim3(256), 0, s, g->pyr, g->stride, g->N, g->solid,
-                       g->octmin);
+    hipLaunchKernelGGL(k_probe_flags, dim3((unsigned)g->P), dim3(256), 0, s, g->pyr, g->stride, g->N,
+                       g->desc.spacing[0], g->desc.spacing[1], g->desc.spacing[2], g->solid, g->octmin);
     HIP_TRY(hipGetLastError());
     return PT_OK;
 }
