@@ -37,10 +37,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_fwd_1080p_traffic.md")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources with comments and spacing removed: a change of code, not
+    of its comments, invalidates the committed counter summaries."""
     h = hashlib.sha256()
     for f in ("probetrace.hip", "trace_device.h", "bake_device.h"):
-        with open(os.path.join(ROOT, "paper_2507_14624_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2507_14624_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -633,8 +633,8 @@ __device__ __forceinline__ uint32_t cage_order(const GridDev &g, const int cell[
 
 // A cell's cage word: bits 0-23 the corner codes to trace, closest to the eye first (3 bits
 // each), bits 24-27 how many, bit 28 set when codes among the first max_probes were left
-// out because their probes answer UNKNOWN for every ray of the view that reaches them (see
-// k_cage_order).
+// out because their probes answer UNKNOWN for every ray of the view that reaches them;
+// probes that answer MISS for all of them are left out without a mark (see k_cage_order).
 constexpr uint32_t kCageUnknown = 1u << 28;
 __device__ __forceinline__ uint32_t cage_word(uint32_t codes, int ranks) {
     return (codes & 0xffffffu) | ((uint32_t)ranks << 24);
@@ -772,8 +772,8 @@ __device__ void trace_ray(const GridDev &g, const Level2 &L2, const R X[3], cons
         }
         // the cage of one level, closest to the eye first; true on a HIT
         auto cage_walk = [&](const GridDev &G, const int cl[3], uint32_t ord, int lev) -> bool {
-            // probes left out of the word would each have answered UNKNOWN, which only
-            // matters for a ray that hits nothing at all
+            // the bit stands for left-out probes that would have answered UNKNOWN, which only
+            // matters for a ray that hits nothing at all (left-out MISS probes change nothing)
             if (ord & kCageUnknown) any_unknown = true;
             const int ranks = (int)((ord >> 24) & 15u);
             for (int rk = 0; rk < ranks; ++rk) {
